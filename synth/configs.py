@@ -1,0 +1,144 @@
+"""Workload descriptions: geometry numbers, frequency grids and seeds.
+
+Each workload is a stack of ``n_layers`` pixel grids (``nx`` by ``ny`` square
+pixels of side ``a``), layer l lying in the plane z = -l*h, embedded in a
+homogeneous medium of relative permittivity ``eps_r`` and loss tangent
+``tan_d``.  Ports sit at the middle cell of a grid side on a given layer.
+Optional vias join layers 0 and 1 at listed (x, y) sites.
+
+The numbers follow the paper's workloads where it gives them (Table I stack
+heights, the Rogers 4350B permittivity in Section IV, the 3-9 GHz FoM window
+of Section III-B) and are otherwise chosen to be of the same shape.  None of
+this is arithmetic of the method; it only says what to build.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .rng import bernoulli_map, pair_flips_3x3, permutation, single_flips
+
+SIDES = ("right", "top", "left", "bottom")
+
+
+@dataclass(frozen=True)
+class PortSpec:
+    side: str  # one of SIDES
+    layer: int
+
+
+@dataclass(frozen=True)
+class WorkloadSpec:
+    name: str
+    n_layers: int
+    nx: int
+    ny: int
+    a: float  # pixel side, metres
+    h: float  # layer spacing, metres
+    eps_r: float
+    tan_d: float
+    ports: tuple
+    n_freq: int
+    f_lo: float
+    f_hi: float
+    seed: int
+    density: float = 0.5
+    n_vias: int = 0
+    z0: float = 50.0
+    candidates: str = "single"  # "single" or "pair3x3"
+
+    @property
+    def n_cells(self) -> int:
+        return self.n_layers * self.nx * self.ny
+
+    @property
+    def freqs(self) -> np.ndarray:
+        return np.linspace(self.f_lo, self.f_hi, self.n_freq)
+
+    def via_sites(self) -> list:
+        """(x, y) sites of the vias, the first n_vias cells of a seeded permutation."""
+        if self.n_vias == 0:
+            return []
+        perm = permutation(self.nx * self.ny, self.seed * 1000 + 7)
+        return [(int(c % self.nx), int(c // self.nx)) for c in perm[: self.n_vias]]
+
+    def base_map(self) -> np.ndarray:
+        return bernoulli_map(self.n_cells, self.density, self.seed)
+
+    def flips(self):
+        """(offsets, cells) CSR of the candidate flips for one search step."""
+        if self.candidates == "single":
+            return single_flips(np.arange(self.n_cells))
+        if self.candidates == "pair3x3":
+            return pair_flips_3x3(self.n_layers, self.nx, self.ny)
+        raise ValueError(self.candidates)
+
+    def uneven_batch(self, n_maps: int = 8, per_map: int = 100, p0: float = 0.55, dp: float = 0.04):
+        """Maps of rising density, each with ``per_map`` single flips.
+
+        Single flips change the active count by a handful of basis functions,
+        so a spread of active sizes needs several base maps.  Returns a list of
+        (map, offsets, cells).
+        """
+        out = []
+        for i in range(n_maps):
+            m = bernoulli_map(self.n_cells, p0 + dp * i, self.seed * 100 + i + 1)
+            cells = permutation(self.n_cells, self.seed * 100 + 50 + i)[:per_map]
+            off, cl = single_flips(np.sort(cells))
+            out.append((m, off, cl))
+        return out
+
+
+def _p(*pairs):
+    return tuple(PortSpec(s, l) for s, l in pairs)
+
+
+SPECS = {
+    # One metal layer of 8x8 one-millimetre pixels in free space, two ports on
+    # opposite sides, 11 frequencies over 1-6 GHz; one sweep of 64 single flips.
+    "plain8": WorkloadSpec(
+        name="plain8", n_layers=1, nx=8, ny=8, a=1.0e-3, h=0.0, eps_r=1.0, tan_d=0.0,
+        ports=_p(("right", 0), ("left", 0)), n_freq=11, f_lo=1.0e9, f_hi=6.0e9, seed=1,
+    ),
+    # Two layers of 20x20 half-millimetre pixels in a lossy dielectric, three
+    # ports (common right, low band top, high band left), 13 vias, 101
+    # frequencies over 1-8 GHz; one sweep of all 800 single flips.
+    "batched20": WorkloadSpec(
+        name="batched20", n_layers=2, nx=20, ny=20, a=0.5e-3, h=0.5e-3, eps_r=3.5, tan_d=0.002,
+        ports=_p(("right", 0), ("top", 0), ("left", 0)), n_freq=101, f_lo=1.0e9, f_hi=8.0e9,
+        seed=2, n_vias=13,
+    ),
+    # Three layers of 24x24 pixels with the 0.4866 mm stack of Table I in
+    # Rogers 4350B; ports on three different layers; 1728 single flips.
+    "stress24": WorkloadSpec(
+        name="stress24", n_layers=3, nx=24, ny=24, a=0.3e-3, h=0.4866e-3, eps_r=3.66, tan_d=0.004,
+        ports=_p(("right", 1), ("left", 2), ("left", 0)), n_freq=101, f_lo=1.0e9, f_hi=8.0e9, seed=3,
+    ),
+    # Three layers of 32x32 pixels, 201 frequencies over 0.5-10 GHz, pair flips
+    # in 3x3 neighbourhoods.
+    "ceiling32": WorkloadSpec(
+        name="ceiling32", n_layers=3, nx=32, ny=32, a=0.3e-3, h=0.4866e-3, eps_r=3.66, tan_d=0.004,
+        ports=_p(("right", 1), ("left", 2), ("left", 0)), n_freq=201, f_lo=0.5e9, f_hi=10.0e9,
+        seed=5, candidates="pair3x3",
+    ),
+    # Small cases for CPU tests.
+    "tiny3": WorkloadSpec(
+        name="tiny3", n_layers=1, nx=3, ny=3, a=1.0e-3, h=0.0, eps_r=1.0, tan_d=0.0,
+        ports=_p(("right", 0), ("left", 0)), n_freq=5, f_lo=3.5e9, f_hi=5.5e9, seed=11,
+    ),
+    "tiny4x2": WorkloadSpec(
+        name="tiny4x2", n_layers=2, nx=4, ny=4, a=0.5e-3, h=0.5e-3, eps_r=3.5, tan_d=0.002,
+        ports=_p(("right", 0), ("top", 0), ("left", 1)), n_freq=4, f_lo=5.0e9, f_hi=7.0e9,
+        seed=12, n_vias=3,
+    ),
+    "small6x3": WorkloadSpec(
+        name="small6x3", n_layers=3, nx=6, ny=6, a=0.3e-3, h=0.4866e-3, eps_r=3.66, tan_d=0.004,
+        ports=_p(("right", 1), ("left", 2), ("left", 0)), n_freq=5, f_lo=4.0e9, f_hi=8.0e9, seed=13,
+    ),
+}
+
+
+def get_spec(name: str) -> WorkloadSpec:
+    return SPECS[name]
