@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the per-candidate MoM evaluation on one MI355X.
+
+Workload (default): two metal layers of 20 x 20 half-millimetre pixels in a
+lossy dielectric (eps_r 3.5, tan d 0.002), three ports, 13 vias, parent size
+M = 2371, 101 frequencies over 1-8 GHz; one step evaluates all 800
+single-flip candidates of the seeded Bernoulli(0.5) map at every frequency
+(gather, dense LU, S, FoM, argmin).  Inputs are synthetic and resident in HBM
+before timing starts; the parent fill is pre-computation and not timed.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3}
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def lu_flops(N, P):
+    """Algorithmic work of one (candidate, frequency) item: complex LU of the
+    N x N system plus forward and back substitution for P right-hand sides."""
+    N = np.asarray(N, dtype=np.float64)
+    return (8.0 / 3.0) * N ** 3 + 8.0 * P * N ** 2
+
+
+def cpu_baseline(spec, gpu_S, sample_c, seconds):
+    """Time the oracle (as it stands) on a bounded sample of the same
+    workload: its own parent fill at one frequency (not timed), then Eq. 5
+    gather, LAPACK solve, S and the per-frequency FoM terms for a set of
+    candidates, repeated until `seconds` of work; scaled to evaluations/s over
+    all frequencies.  Also returns the sampled max |dS| against the GPU."""
+    from oracle import efie, fom as ofom, geometry, network, search
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    f_idx = int(np.argmin(np.abs(spec.freqs - 5.5e9)))
+    f = spec.freqs[f_idx]
+    st = geometry.build_structure(spec)
+    log(f"cpu baseline: oracle fill at {f / 1e9:.2f} GHz (M = {st.M})")
+    t = time.time()
+    Z = efie.fill(st, f)
+    log(f"cpu baseline: oracle fill took {time.time() - t:.1f} s")
+    base = spec.base_map()
+    off, cells = spec.flips()
+    maps = search.candidate_maps(base, off, cells)
+    pl = search.port_lengths(st)
+    dS = 0.0
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        for c in sample_c:
+            sel = st.active(maps[c])
+            rows = network.port_positions(sel, st.port_bf)
+            S = network.s_parameters(network.reduce_matrix(Z, sel), rows, pl, spec.z0)
+            ofom.rewards(S)
+            if done < len(sample_c):
+                dS = max(dS, float(np.abs(S - gpu_S[c, f_idx]).max()))
+            done += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    per_item = el / done
+    value = 1.0 / (per_item * spec.n_freq)
+    sample = (f"{len(sample_c)} candidates x 1 frequency ({f / 1e9:.2f} GHz), {done} solves in {el:.1f} s, "
+              f"scaled x{spec.n_freq} frequencies per evaluation")
+    return {"value": value, "unit": "evals/s", "cores": int(cores), "kind": "oracle", "sample": sample}, dS
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched20")
+    ap.add_argument("--precision", default="fp64", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fill-threads", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1 (the path shards by frequency "
+              "across GPUs by design, but no multi-GPU run is part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2412_17617_amd import pxd
+    from synth import get_spec
+
+    spec = get_spec(args.workload)
+    freqs = spec.freqs
+    log(f"workload {spec.name}: {spec.n_layers} layers {spec.nx}x{spec.ny}, {spec.n_freq} frequencies")
+    pb = pxd.Problem.from_spec(spec)
+    t = time.time()
+    Z = pb.fill(freqs, n_threads=args.fill_threads)
+    log(f"parent fill (host, {args.fill_threads} threads): M = {pb.M}, {time.time() - t:.1f} s")
+    prec = pxd.PREC_FP64 if args.precision == "fp64" else pxd.PREC_MIXED32
+    ev = pxd.Evaluator(device=0, precision=prec)
+    ev.load_parent(Z, freqs)
+    ev.load_problem(pb, spec.z0)
+    ev.set_fom_paper()
+    del Z
+
+    dev = torch.device("cuda:0")
+    base = spec.base_map()
+    off, cells = spec.flips()
+    C = len(off) - 1
+    P = len(spec.ports)
+    t_base = torch.from_numpy(base).to(dev)
+    t_off = torch.from_numpy(off).to(dev)
+    t_cells = torch.from_numpy(cells).to(dev)
+    S_out = torch.empty((C, spec.n_freq, P, P, 2), dtype=torch.float64, device=dev)
+    fom_out = torch.empty(C, dtype=torch.float64, device=dev)
+    st_out = torch.empty(C, dtype=torch.int32, device=dev)
+    am_out = torch.empty(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    N, _ = ev.expand(base, off, cells)
+    flops_per_launch = float(lu_flops(N, P).sum() * spec.n_freq)
+    log(f"candidates {C}, active size {N.min()}..{N.max()}, {flops_per_launch / 1e12:.1f} TFLOP per step")
+
+    def step():
+        ev.evaluate_flips_device(stream, t_base, t_off, t_cells, S_out, fom_out, st_out, am_out)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kernel_ms = []
+    e0.record(stream)
+    for i in range(args.steps):
+        step()
+        kernel_ms.append(ev.stats()["ms_solve"])
+        log(f"step {i + 1}/{args.steps}: evaluator kernel {kernel_ms[-1]:.1f} ms")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = st_out.cpu().numpy()
+    value = C / (ms / 1e3)
+    k_ms = float(np.mean(kernel_ms))
+    achieved = flops_per_launch / (k_ms / 1e3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    out = {
+        "metric": "pixel-map evals/sec (all freqs, S+FoM) vs FP64 plain, at max |dS|<=1e-4",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{spec.name}: {spec.n_layers} layers {spec.nx}x{spec.ny} pixels, M={pb.M}, "
+                        f"{spec.n_freq} freqs {spec.f_lo / 1e9:g}-{spec.f_hi / 1e9:g} GHz, {C} single flips",
+            "precision": args.precision,
+            "candidates": C,
+            "frequencies": spec.n_freq,
+            "active_size": [int(N.min()), int(N.max())],
+            "status_nonzero": int(np.count_nonzero(st)),
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "kernel": "k_eval_plain" if args.precision == "fp64" else "k_eval_mixed",
+            "kernel_ms": k_ms,
+        },
+    }
+    if not args.no_cpu_baseline:
+        sample_c = list(range(0, C, max(1, C // 16)))[:16]
+        S_host = torch.view_as_complex(S_out[sample_c].contiguous()).cpu().numpy()
+        S_full = np.zeros((C,) + S_host.shape[1:], np.complex128)
+        S_full[sample_c] = S_host
+        cb, dS = cpu_baseline(spec, S_full, sample_c, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["config"]["max_dS_vs_oracle_sample"] = dS
+    ev.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * pxd.h -- C ABI of the MI355X (gfx950) evaluator for pixelated multi-layer
+ * MoM structures (arXiv 2412.17617).
+ *
+ * The library evaluates batches of candidate pixel maps: for every candidate
+ * and every frequency it selects the active RWG functions, gathers their
+ * rows and columns out of a precomputed parent impedance matrix (Eqs. 3-5),
+ * solves the dense system Z I = V for every port (Eq. 2), forms the
+ * S-parameters (Eqs. 6-7) and reduces them to the figure of merit of
+ * Eqs. 8-9.  A native host routine builds the structure (mesh, basis-function
+ * classification of Section II-C) and fills the parent matrices.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: PXD_OK (0) or a negative PXD_E* code.  Nothing throws
+ *    across the ABI.  pxd_last_error() returns a message for the last failure
+ *    on a context (or on the thread, for calls that take no context).
+ *  - Complex numbers are interleaved (re, im) doubles (complex128) or floats.
+ *  - Matrices are row-major; parent matrices are symmetric so row and column
+ *    order coincide.
+ *  - Host pointers passed in are only read during the call; the library
+ *    copies what it keeps.  Output host buffers are owned by the caller.
+ *  - *_device entry points take device pointers (for example memory owned by
+ *    PyTorch) and a hipStream_t passed as void*; work is ordered on that
+ *    stream and the call returns without synchronising it.  Device buffers
+ *    are borrowed only for the duration of the call.
+ *  - Units are SI: metre, hertz, ohm.
+ *  - One context must not be used from two host threads at once.
+ */
+#ifndef PXD_H
+#define PXD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PXD_OK 0
+#define PXD_EINVAL (-1)     /* bad argument (null pointer, size out of range) */
+#define PXD_ENOMEM (-2)     /* host or device allocation failed */
+#define PXD_ENOTLOADED (-3) /* parent matrices, map or FoM table not loaded */
+#define PXD_EDEVICE (-4)    /* HIP runtime error */
+#define PXD_ESHAPE (-5)     /* inconsistent sizes between loaded objects */
+
+/* Basis-function classes (Section II-C, Fig. 2(a)); a function is active iff
+ * every cell it references (cell_a, cell_b; -1 = none) is on. */
+#define PXD_KIND_ALWAYS 0  /* feed and port functions */
+#define PXD_KIND_INNER 1   /* inside one pixel */
+#define PXD_KIND_INTER 2   /* between two side-adjacent pixels */
+#define PXD_KIND_PIXPORT 3 /* between a feed and its adjacent pixel */
+#define PXD_KIND_VIA 4     /* vertical strip joining layers 0 and 1 */
+
+/* Per-item status codes written by the evaluator. */
+#define PXD_STATUS_OK 0
+#define PXD_STATUS_FALLBACK 1     /* mixed precision did not converge; FP64 result returned */
+#define PXD_STATUS_NONFINITE (-1) /* a non-finite value reached S */
+#define PXD_STATUS_SINGULAR (-2)  /* an exactly zero pivot was met */
+
+/* Arithmetic of the dense solve. */
+#define PXD_PREC_FP64 0    /* complex128 LU, no refinement ("plain") */
+#define PXD_PREC_MIXED32 1 /* complex64 LU + FP64 residual and iterative refinement */
+
+/* ---------------------------------------------------------------- structure */
+
+/* Workload geometry.  Layer l lies in z = -l*h; pixel (l, x, y) covers
+ * [x a, (x+1) a] x [y a, (y+1) a].  Each pixel carries two triangles with
+ * checkerboard-alternating diagonals.  Port k sits at the middle cell of grid
+ * side port_side[k] (0 right, 1 top, 2 left, 3 bottom) on layer port_layer[k].
+ * Via v joins cell (0, via_x[v], via_y[v]) and cell (1, ...), hanging under
+ * the cell's lower side. */
+typedef struct pxd_geometry {
+  int32_t n_layers, nx, ny;
+  double a, h;
+  double eps_r, tan_d; /* homogeneous medium: eps = eps0 eps_r (1 - j tan_d) */
+  int32_t n_ports;
+  const int32_t* port_side;
+  const int32_t* port_layer;
+  int32_t n_vias;
+  const int32_t* via_x;
+  const int32_t* via_y;
+} pxd_geometry;
+
+typedef struct pxd_problem pxd_problem;
+
+/* Build mesh and RWG functions in canonical order: inner (cell order),
+ * inter-pixel horizontal then vertical, pixel-port, via, feed diagonals, port
+ * edges last (port order).  *out is owned by the caller (pxd_problem_destroy). */
+int pxd_problem_create(const pxd_geometry* g, pxd_problem** out);
+void pxd_problem_destroy(pxd_problem* p);
+/* Parent size M, cell count and port count. */
+int pxd_problem_sizes(const pxd_problem* p, int32_t* M, int32_t* n_cells, int32_t* n_ports);
+/* Classification arrays (length M each; port arrays length n_ports):
+ * kind, cell_a, cell_b, the parent index of each port's delta-gap function
+ * and its edge length.  Any pointer may be NULL to skip that array. */
+int pxd_problem_classification(const pxd_problem* p, uint8_t* kind, int32_t* cell_a, int32_t* cell_b,
+                               int32_t* port_bf, double* port_len);
+/* Fill the parent impedance matrices of the EFIE (Eqs. 1-2), mixed-potential
+ * Galerkin with RWG functions, kernel exp(-jkR)/(4 pi R), 4-point triangle
+ * rule, closed-form 1/R extraction on near pairs; upper triangle computed and
+ * mirrored.  Z_out: F x M x M complex128, row-major, caller-owned (host).
+ * n_threads <= 0 uses every hardware thread.  Host only; needs no GPU. */
+int pxd_problem_fill(const pxd_problem* p, int32_t F, const double* freqs_hz, double* Z_out, int32_t n_threads);
+
+/* ---------------------------------------------------------------- evaluator */
+
+typedef struct pxd_options {
+  int32_t device;          /* HIP device ordinal */
+  int32_t precision;       /* PXD_PREC_* */
+  int32_t ir_max_iter;     /* refinement iterations before FP64 fallback (default 10) */
+  double ir_tol;           /* per-entry relative port-current tolerance (default 1e-10) */
+  int32_t wg_per_cu;       /* persistent workgroups per compute unit (0 = 2) */
+  int32_t panel;           /* LU panel width, 16 or 32 (0 = 32) */
+} pxd_options;
+
+typedef struct pxd_ctx pxd_ctx;
+
+/* A FoM term (Eq. 9 in closed form): value = 10^log10_factor * |S_ij|^power,
+ * summed over the frequencies whose band equals `band`.  i, j are 0-based. */
+typedef struct pxd_fom_term {
+  int32_t band;
+  int32_t i, j;
+  double log10_factor;
+  double power;
+} pxd_fom_term;
+
+typedef struct pxd_stats {
+  int64_t items;          /* (candidate, frequency) solves in the last call */
+  int64_t fallbacks;      /* items re-solved in FP64 after refinement failed */
+  int64_t ir_iterations;  /* refinement iterations summed over items */
+  int32_t max_active;     /* largest active size N in the last call */
+  int32_t min_active;
+  double ms_expand, ms_solve, ms_fallback, ms_fom; /* stage times of the last call (events) */
+} pxd_stats;
+
+int pxd_create(const pxd_options* opt, pxd_ctx** out);
+void pxd_destroy(pxd_ctx* ctx);
+const char* pxd_last_error(const pxd_ctx* ctx); /* ctx may be NULL: thread-local last error */
+
+/* Parent matrices: F x M x M complex128 row-major host array, frequencies in Hz.
+ * The library keeps a device copy (and a complex64 copy in MIXED32 mode). */
+int pxd_load_parent(pxd_ctx* ctx, int32_t M, int32_t F, const double* freqs_hz, const double* Z);
+
+/* Pixel-to-RWG map (Section II-C): per parent function its kind and the cells
+ * it needs (cell_b = -1 if one); P ports with their parent function index
+ * (ports must be the last P functions, in port order) and edge length; Z0. */
+int pxd_load_map(pxd_ctx* ctx, int32_t n_cells, int32_t M, const uint8_t* kind, const int32_t* cell_a,
+                 const int32_t* cell_b, int32_t P, const int32_t* port_bf, const double* port_len, double z0);
+
+/* FoM table and per-frequency band id (-1 = no band). */
+int pxd_set_fom(pxd_ctx* ctx, int32_t n_terms, const pxd_fom_term* terms, const int8_t* band_of_freq);
+/* The FoM of Eqs. 8-9 with the Section III-B bands (p1 = [5.15, 5.925] GHz,
+ * p2 = [6.425, 7.125] GHz, f_i between them, f_s = the rest of [3, 9] GHz);
+ * terms whose S entry exceeds the port count are dropped. */
+int pxd_set_fom_paper(pxd_ctx* ctx);
+
+/* Evaluate candidates given as flips of a base map: candidate c toggles cells
+ * cells[offsets[c] .. offsets[c+1]).  Outputs (host, caller-owned, any may be
+ * NULL): S_out n_cand x F x P x P complex128; fom_out n_cand; status n_cand
+ * (worst item status); argmin_out the lowest-index minimum-FoM candidate. */
+int pxd_evaluate_flips(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,
+                       const int32_t* cells, double* S_out, double* fom_out, int32_t* status,
+                       int32_t* argmin_out);
+
+/* Same with device pointers on `stream` (a hipStream_t); n_flips is the
+ * length of `cells`.  argmin_out is a device int32. */
+int pxd_evaluate_flips_device(pxd_ctx* ctx, void* stream, const uint8_t* base_map, int32_t n_cand,
+                              const int32_t* offsets, const int32_t* cells, int32_t n_flips, double* S_out,
+                              double* fom_out, int32_t* status, int32_t* argmin_out);
+
+/* Row a1 alone: active index sets (Eq. 3) of each candidate.  N_out n_cand;
+ * idx_out n_cand x M (row c holds N_out[c] ascending indices).  Host buffers. */
+int pxd_expand(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,
+               const int32_t* cells, int32_t* N_out, int32_t* idx_out);
+
+/* Row a2 alone: the gathered matrix Z_parent(f)[I, I] (Eq. 5) for index set
+ * idx (N ascending parent indices) at frequency index f.  ZA_out: N x N
+ * complex128 host buffer. */
+int pxd_gather(pxd_ctx* ctx, int32_t f, int32_t N, const int32_t* idx, double* ZA_out);
+
+int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PXD_H */

@@ -1,0 +1,681 @@
+// gfx950 kernels of the per-candidate evaluation.
+//
+//  expand   : candidate map -> ascending active index set (Eqs. 3-4, Section II-C)
+//  order    : candidates by decreasing active size (largest first)
+//  eval     : persistent workgroups; per (candidate, frequency) item:
+//             gather Z_A = Z_f[I, I] (Eq. 5) with the port loads and the
+//             excitation columns, blocked LU with partial pivoting (Eq. 2),
+//             S-parameters from the port currents (Eqs. 6-7)
+//  fom      : Eqs. 8-9 reduced over frequency, one thread per candidate
+//  argmin   : lowest-index minimum (Algorithm 1)
+//
+// LU layout: each workgroup owns one workspace slot holding the item's
+// matrix row-major (leading dimension ld).  The active functions keep their
+// parent order, so the P port functions are the last P unknowns.  Eliminating
+// the first N-P columns of the augmented [Z_A | V] leaves the P x P Schur
+// system of the port unknowns, which is solved directly: no back substitution
+// and no storage of L or U is needed for the FP64 path.
+//
+// Panel factorisation: panels of NB = 32 columns, factored in sub-blocks of
+// SB columns held in registers (Q rows per thread, N <= 256 Q, Q SB <= 16); the pivot
+// search is a wave shuffle reduction plus one LDS exchange per column.  Row
+// interchanges are applied to the trailing columns lazily, fused with the
+// triangular solve of the U block.  The trailing update A22 -= L21 U12 is a
+// complex GEMM made of four real 16x16x4 MFMAs per complex product; each
+// wave owns 32 x 32 output tiles and keeps its L21 fragments in registers
+// across a run of tiles of the same block row.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace pxd {
+
+constexpr int NB = 32;
+
+template <typename R>
+struct LuShared {
+  using T = typename Cx<R>::T;
+  T prow[NB];
+  T crow[NB];
+  T L11[NB * NB];
+  T Usub[NB * NB];
+  R red_v[kWaves];
+  int red_i[kWaves];
+  int piv[NB];
+  int bad;
+};
+
+// ------------------------------------------------------------------ expand
+
+__global__ __launch_bounds__(256) void k_expand(const uint8_t* __restrict__ base, int n_cells,
+                                                const int* __restrict__ off, const int* __restrict__ cells,
+                                                const int* __restrict__ cell_a, const int* __restrict__ cell_b,
+                                                int M, int* __restrict__ Nc, int* __restrict__ Ilist) {
+  extern __shared__ uint8_t smap[];
+  __shared__ int wave_tot[4];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int i = tid; i < n_cells; i += 256) smap[i] = base[i] ? 1 : 0;
+  __syncthreads();
+  if (tid == 0)
+    for (int i = off[c]; i < off[c + 1]; ++i) {
+      const int cell = cells[i];
+      if (cell >= 0 && cell < n_cells) smap[cell] ^= 1;
+    }
+  __syncthreads();
+  int running = 0;
+  int* out = Ilist + (size_t)c * M;
+  for (int m0 = 0; m0 < M; m0 += 256) {
+    const int m = m0 + tid;
+    bool on = false;
+    if (m < M) {
+      const int a = cell_a[m], b = cell_b[m];
+      on = (a < 0 || smap[a]) && (b < 0 || smap[b]);
+    }
+    const unsigned long long mask = __ballot(on);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_tot[wid] = __popcll(mask);
+    __syncthreads();
+    int pre = running;
+    for (int w = 0; w < wid; ++w) pre += wave_tot[w];
+    if (on) out[pre + before] = m;
+    running += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+    __syncthreads();
+  }
+  if (tid == 0) Nc[c] = running;
+}
+
+// rank of candidate c when sorted by decreasing N, ties by index
+__global__ void k_order(const int* __restrict__ Nc, int C, int* __restrict__ order) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int n = Nc[c];
+  int rank = 0;
+  for (int j = 0; j < C; ++j) {
+    const int nj = Nc[j];
+    rank += (nj > n) || (nj == n && j < c);
+  }
+  order[rank] = c;
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ gather
+
+__global__ void k_gather(const double2* __restrict__ Zf, int M, const int* __restrict__ idx, int N,
+                         double2* __restrict__ out) {
+  const int r = blockIdx.x;
+  if (r >= N) return;
+  const double2* zrow = Zf + (size_t)idx[r] * M;
+  for (int s = threadIdx.x; s < N; s += blockDim.x) out[(size_t)r * N + s] = zrow[idx[s]];
+}
+
+__global__ void k_to_c64(const double2* __restrict__ in, float2* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double2 v = in[i];
+    out[i] = float2{(float)v.x, (float)v.y};
+  }
+}
+
+// Z_A = Z_f[I, I] into the slot, plus the Z0 loads of the port functions and,
+// for the augmented system, the excitation columns V (1 V source EMF in each
+// port gap: V[row of port j, j] = l_j).
+template <typename T, typename TP>
+__device__ __forceinline__ void gather_item(T* __restrict__ W, int ld, const TP* __restrict__ Zf, int M, const int* sI, int N,
+                            int P, const double* __restrict__ plen, double z0, bool augment) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int r = wid; r < N; r += kWaves) {
+    const TP* zrow = Zf + (size_t)sI[r] * M;
+    T* wrow = W + (size_t)r * ld;
+    int s = lane;
+    for (; s + 192 < N; s += 256) {
+      const TP v0 = zrow[sI[s]], v1 = zrow[sI[s + 64]], v2 = zrow[sI[s + 128]], v3 = zrow[sI[s + 192]];
+      wrow[s] = T{(decltype(T::x))v0.x, (decltype(T::x))v0.y};
+      wrow[s + 64] = T{(decltype(T::x))v1.x, (decltype(T::x))v1.y};
+      wrow[s + 128] = T{(decltype(T::x))v2.x, (decltype(T::x))v2.y};
+      wrow[s + 192] = T{(decltype(T::x))v3.x, (decltype(T::x))v3.y};
+    }
+    for (; s < N; s += 64) {
+      const TP v = zrow[sI[s]];
+      wrow[s] = T{(decltype(T::x))v.x, (decltype(T::x))v.y};
+    }
+    if (augment && lane < P) wrow[N + lane] = T{(r == N - P + lane) ? (decltype(T::x))plen[lane] : 0, 0};
+  }
+  __syncthreads();
+  if (tid < P) {
+    const int r = N - P + tid;
+    W[(size_t)r * ld + r].x += (decltype(T::x))(z0 * plen[tid] * plen[tid]);
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ LU pieces
+
+// Unblocked LU with partial pivoting of the sub-panel rows [c0, N), columns
+// [c0, c0 + sbw), held in registers: thread t owns rows c0 + t + 256 q.
+template <typename R, int Q, int SB>
+__device__ __forceinline__ void factor_subpanel(typename Cx<R>::T* __restrict__ W, int ld, int N, int c0, int sbw,
+                                LuShared<R>& sm, int pbase) {
+  using T = typename Cx<R>::T;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  T reg[Q][SB];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = c0 + tid + kThreads * q;
+#pragma unroll
+    for (int j = 0; j < SB; ++j) reg[q][j] = (r < N && j < sbw) ? W[(size_t)r * ld + c0 + j] : T{0, 0};
+  }
+#pragma unroll
+  for (int j = 0; j < SB; ++j) {
+    if (j < sbw) {
+      const int c = c0 + j;
+      R best = R(-1);
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int r = c0 + tid + kThreads * q;
+        if (r >= c && r < N) {
+          const R v = fabs(reg[q][j].x) + fabs(reg[q][j].y);
+          if (v > best) {
+            best = v;
+            bi = r;
+          }
+        }
+      }
+      wave_argmax(best, bi);
+      if (lane == 0) {
+        sm.red_v[wid] = best;
+        sm.red_i[wid] = bi;
+      }
+      __syncthreads();
+      best = sm.red_v[0];
+      bi = sm.red_i[0];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) {
+        const R ov = sm.red_v[w];
+        const int oi = sm.red_i[w];
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (bi >= N) bi = c;  // no finite candidate: keep the diagonal, flagged below
+      const int p = bi;
+      const int oc = c - c0, op = p - c0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int rr = tid + kThreads * q;
+        if (rr == op) {
+#pragma unroll
+          for (int jj = 0; jj < SB; ++jj) sm.prow[jj] = reg[q][jj];
+        }
+        if (rr == oc) {
+#pragma unroll
+          for (int jj = 0; jj < SB; ++jj) sm.crow[jj] = reg[q][jj];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int rr = tid + kThreads * q;
+        if (rr == oc) {
+#pragma unroll
+          for (int jj = 0; jj < SB; ++jj) reg[q][jj] = sm.prow[jj];
+        } else if (rr == op) {
+#pragma unroll
+          for (int jj = 0; jj < SB; ++jj) reg[q][jj] = sm.crow[jj];
+        }
+      }
+      const T pv = sm.prow[j];
+      if (tid == 0) {
+        sm.piv[pbase + j] = p;
+        if (!(fabs(pv.x) + fabs(pv.y) > R(0))) sm.bad = 1;  // zero or non-finite pivot
+      }
+      const T inv = crecip(pv);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int r = c0 + tid + kThreads * q;
+        if (r > c && r < N) {
+          const T l = cmul(reg[q][j], inv);
+          reg[q][j] = l;
+#pragma unroll
+          for (int jj = j + 1; jj < SB; ++jj) reg[q][jj] = cfms(reg[q][jj], l, sm.prow[jj]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = c0 + tid + kThreads * q;
+    if (r < N) {
+#pragma unroll
+      for (int j = 0; j < SB; ++j)
+        if (j < sbw) W[(size_t)r * ld + c0 + j] = reg[q][j];
+    }
+  }
+}
+
+// Factor panel columns [k, k + kb) over rows [k, N); pivots of the panel end
+// in sm.piv[0 .. kb) (absolute rows), applied to every panel column.
+template <typename R, int Q, int SB>
+__device__ __forceinline__ void factor_panel(typename Cx<R>::T* __restrict__ W, int ld, int N, int k, int kb, LuShared<R>& sm) {
+  using T = typename Cx<R>::T;
+  const int tid = threadIdx.x;
+  for (int s = 0; s < kb; s += SB) {
+    const int c0 = k + s, sbw = min(SB, kb - s);
+    factor_subpanel<R, Q, SB>(W, ld, N, c0, sbw, sm, s);
+    __syncthreads();
+    // this sub-block's interchanges on the other columns of the panel
+    for (int t = tid; t < kb; t += kThreads) {
+      const int col = k + t;
+      if (col >= c0 && col < c0 + sbw) continue;
+      for (int j = 0; j < sbw; ++j) {
+        const int r = c0 + j, p = sm.piv[s + j];
+        if (p != r) {
+          const T a = W[(size_t)r * ld + col];
+          W[(size_t)r * ld + col] = W[(size_t)p * ld + col];
+          W[(size_t)p * ld + col] = a;
+        }
+      }
+    }
+    __syncthreads();
+    const int w2 = kb - s - sbw;
+    if (w2 > 0) {
+      // U block of the columns right of the sub-block: unit-lower solve
+      for (int t = tid; t < w2; t += kThreads) {
+        const int col = c0 + sbw + t;
+        T u[SB];
+#pragma unroll
+        for (int i = 0; i < SB; ++i) u[i] = (i < sbw) ? W[(size_t)(c0 + i) * ld + col] : T{0, 0};
+#pragma unroll
+        for (int i = 1; i < SB; ++i) {
+          if (i < sbw) {
+            T acc = u[i];
+#pragma unroll
+            for (int j = 0; j < i; ++j) acc = cfms(acc, W[(size_t)(c0 + i) * ld + c0 + j], u[j]);
+            u[i] = acc;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+          if (i < sbw) {
+            W[(size_t)(c0 + i) * ld + col] = u[i];
+            sm.Usub[i * NB + t] = u[i];
+          }
+      }
+      __syncthreads();
+      for (int r = c0 + sbw + tid; r < N; r += kThreads) {
+        T l[SB];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) l[j] = (j < sbw) ? W[(size_t)r * ld + c0 + j] : T{0, 0};
+        T* row = W + (size_t)r * ld + c0 + sbw;
+        for (int t = 0; t < w2; ++t) {
+          T acc = row[t];
+#pragma unroll
+          for (int j = 0; j < SB; ++j) acc = cfms(acc, l[j], sm.Usub[j * NB + t]);
+          row[t] = acc;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Interchanges of the panel on the trailing columns [k + kb, ncols), then
+// U12 = L11^-1 A12 (unit lower), one thread per column, in blocks of 8 rows
+// held in registers.
+template <typename R>
+__device__ __forceinline__ void swap_trsm(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int ncols,
+                                          LuShared<R>& sm) {
+  using T = typename Cx<R>::T;
+  constexpr int B = 8;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kb * kb; e += kThreads) {
+    const int i = e / kb, j = e - i * kb;
+    sm.L11[i * NB + j] = (j < i) ? W[(size_t)(k + i) * ld + k + j] : T{0, 0};
+  }
+  __syncthreads();
+  for (int col = k + kb + tid; col < ncols; col += kThreads) {
+    for (int i = 0; i < kb; ++i) {
+      const int r = k + i, p = sm.piv[i];
+      if (p != r) {
+        const T a = W[(size_t)r * ld + col];
+        W[(size_t)r * ld + col] = W[(size_t)p * ld + col];
+        W[(size_t)p * ld + col] = a;
+      }
+    }
+    for (int b0 = 0; b0 < kb; b0 += B) {
+      T u[B];
+#pragma unroll
+      for (int i = 0; i < B; ++i) u[i] = (b0 + i < kb) ? W[(size_t)(k + b0 + i) * ld + col] : T{0, 0};
+      for (int j = 0; j < b0; ++j) {  // contributions of the solved rows above the block
+        const T uj = W[(size_t)(k + j) * ld + col];
+#pragma unroll
+        for (int i = 0; i < B; ++i) u[i] = cfms(u[i], sm.L11[(b0 + i) * NB + j], uj);
+      }
+#pragma unroll
+      for (int i = 1; i < B; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) u[i] = cfms(u[i], sm.L11[(b0 + i) * NB + b0 + j], u[j]);
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+        if (b0 + i < kb) W[(size_t)(k + b0 + i) * ld + col] = u[i];
+    }
+  }
+  __syncthreads();
+}
+
+// A22 -= L21 U12 on rows [k + kb, N), columns [k + kb, ncols).
+template <typename R>
+__device__ __forceinline__ void trailing_update(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int N, int ncols) {
+  using T = typename Cx<R>::T;
+  using MF = Mfma<R>;
+  using acc_t = typename MF::acc_t;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r0 = k + kb, c0 = k + kb;
+  const int mr = N - r0, nc = ncols - c0;
+  if (mr <= 0 || nc <= 0) return;
+  const int tmn = (mr + 31) >> 5, tnn = (nc + 31) >> 5;
+  const int nt = tmn * tnn;
+  const int per = (nt + kWaves - 1) / kWaves;
+  const int t0 = wid * per, t1 = min(nt, t0 + per);
+  const int kqn = (kb + 3) >> 2;
+  int cur = -1;
+  T afr[2][NB / 4];
+  for (int t = t0; t < t1; ++t) {
+    const int tm = t / tnn, tn = t - tm * tnn;
+    if (tm != cur) {
+      cur = tm;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int kq = 0; kq < NB / 4; ++kq) {
+          const int r = r0 + 32 * tm + 16 * a + (lane & 15);
+          const int kk = 4 * kq + (lane >> 4);
+          afr[a][kq] = (r < N && kk < kb) ? W[(size_t)r * ld + k + kk] : T{0, 0};
+        }
+    }
+    acc_t cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = acc_t{0, 0, 0, 0};
+        ci[a][b] = acc_t{0, 0, 0, 0};
+      }
+#pragma unroll
+    for (int kq = 0; kq < NB / 4; ++kq) {
+      if (kq < kqn) {
+        T bfr[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int kk = 4 * kq + (lane >> 4);
+          const int col = c0 + 32 * tn + 16 * b + (lane & 15);
+          bfr[b] = (kk < kb && col < ncols) ? W[(size_t)(k + kk) * ld + col] : T{0, 0};
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = MF::run(afr[a][kq].x, bfr[b].x, cr[a][b]);
+            cr[a][b] = MF::run(-afr[a][kq].y, bfr[b].y, cr[a][b]);
+            ci[a][b] = MF::run(afr[a][kq].x, bfr[b].y, ci[a][b]);
+            ci[a][b] = MF::run(afr[a][kq].y, bfr[b].x, ci[a][b]);
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = r0 + 32 * tm + 16 * a + MF::row(lane, i);
+          const int col = c0 + 32 * tn + 16 * b + (lane & 15);
+          if (r < N && col < ncols) {
+            T* q = W + (size_t)r * ld + col;
+            T v = *q;
+            v.x -= cr[a][b][i];
+            v.y -= ci[a][b][i];
+            *q = v;
+          }
+        }
+  }
+}
+
+// Right-looking blocked LU of columns [0, Ne) of the N x ncols row-major
+// matrix; interchanges touch the panel and the trailing columns only.  When
+// piv_out is given, the pivots are stored there (absolute rows).
+template <typename R, int Q, int SB>
+__device__ __forceinline__ void lu_factor(typename Cx<R>::T* __restrict__ W, int ld, int N, int Ne, int ncols, LuShared<R>& sm,
+                          int* __restrict__ piv_out) {
+  for (int k = 0; k < Ne; k += NB) {
+    const int kb = min(NB, Ne - k);
+    factor_panel<R, Q, SB>(W, ld, N, k, kb, sm);
+    if (piv_out)
+      for (int i = threadIdx.x; i < kb; i += kThreads) piv_out[k + i] = sm.piv[i];
+    swap_trsm<R>(W, ld, k, kb, ncols, sm);
+    trailing_update<R>(W, ld, k, kb, N, ncols);
+    __syncthreads();
+  }
+}
+
+// P x P system of the port unknowns left after eliminating the first N - P
+// columns of [Z_A | V]; thread 0 solves it with partial pivoting and writes
+// S = I - 2 Z0 diag(l) X (Eqs. 6-7).
+__device__ __forceinline__ int port_solve_and_s(const double2* __restrict__ W, int ld, int N, int P,
+                                const double* __restrict__ plen, double z0, double2* __restrict__ S) {
+  __shared__ double2 A[4][8];
+  const int tid = threadIdx.x;
+  if (tid < P * 2 * P) {
+    const int i = tid / (2 * P), j = tid - i * 2 * P;
+    A[i][j] = W[(size_t)(N - P + i) * ld + (N - P + j)];
+  }
+  __syncthreads();
+  int st = PXD_STATUS_OK;
+  if (tid == 0) {
+    for (int c = 0; c < P; ++c) {
+      int p = c;
+      double best = fabs(A[c][c].x) + fabs(A[c][c].y);
+      for (int r = c + 1; r < P; ++r) {
+        const double v = fabs(A[r][c].x) + fabs(A[r][c].y);
+        if (v > best) best = v, p = r;
+      }
+      if (!(best > 0.0)) st = PXD_STATUS_SINGULAR;
+      if (p != c)
+        for (int j = 0; j < 2 * P; ++j) {
+          const double2 t = A[c][j];
+          A[c][j] = A[p][j];
+          A[p][j] = t;
+        }
+      const double2 inv = crecip(A[c][c]);
+      for (int r = c + 1; r < P; ++r) {
+        const double2 l = cmul(A[r][c], inv);
+        for (int j = c; j < 2 * P; ++j) A[r][j] = cfms(A[r][j], l, A[c][j]);
+      }
+    }
+    for (int j = 0; j < P; ++j)
+      for (int i = P - 1; i >= 0; --i) {
+        double2 acc = A[i][P + j];
+        for (int t = i + 1; t < P; ++t) acc = cfms(acc, A[i][t], A[t][P + j]);
+        A[i][P + j] = cmul(acc, crecip(A[i][i]));
+      }
+    bool finite = true;
+    for (int i = 0; i < P; ++i)
+      for (int j = 0; j < P; ++j) {
+        const double2 x = A[i][P + j];
+        double2 s = double2{(i == j ? 1.0 : 0.0) - 2.0 * z0 * plen[i] * x.x, -2.0 * z0 * plen[i] * x.y};
+        finite = finite && isfinite(s.x) && isfinite(s.y);
+        S[i * P + j] = s;
+      }
+    if (!finite) st = PXD_STATUS_NONFINITE;
+  }
+  __syncthreads();
+  return st;
+}
+
+// ------------------------------------------------------------------ evaluator (FP64)
+
+template <int Q, int SB>
+__global__ __launch_bounds__(kThreads, 2) void k_eval_plain(EvalParams p) {
+  using T = double2;
+  __shared__ LuShared<double> sm;
+  __shared__ int sI[kThreads * Q];
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  const int ld = slot_layout(p.nmax, p.P, false).ld;
+  T* W = reinterpret_cast<T*>(p.ws + (size_t)blockIdx.x * p.slot_bytes);
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(p.counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= p.n_items) break;
+    int c, f;
+    if (p.item_list) {
+      const int e = p.item_list[it];
+      c = e / p.F;
+      f = e - c * p.F;
+    } else {
+      f = it / p.C;
+      c = p.order[it - f * p.C];
+    }
+    const int N = p.Nc[c];
+    double2* Sout = p.S + ((size_t)c * p.F + f) * p.P * p.P;
+    if (N > kThreads * Q || N > p.nmax || N < p.P) {  // cannot happen when the host sizes the launch
+      if (tid == 0) p.status[(size_t)c * p.F + f] = PXD_STATUS_NONFINITE;
+      continue;
+    }
+    for (int s = tid; s < N; s += kThreads) sI[s] = p.Ilist[(size_t)c * p.M + s];
+    if (tid == 0) sm.bad = 0;
+    __syncthreads();
+    gather_item<T, double2>(W, ld, p.Z128 + (size_t)f * p.M * p.M, p.M, sI, N, p.P, p.port_len, p.z0, true);
+    lu_factor<double, Q, SB>(W, ld, N, N - p.P, N + p.P, sm, nullptr);
+    int st = port_solve_and_s(W, ld, N, p.P, p.port_len, p.z0, Sout);
+    if (tid == 0) {
+      if (sm.bad && st == PXD_STATUS_OK) st = PXD_STATUS_SINGULAR;
+      p.status[(size_t)c * p.F + f] = st;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ FoM and argmin
+
+__global__ void k_fom(const double2* __restrict__ S, int C, int F, int P, const pxd_fom_term* __restrict__ terms,
+                      const double* __restrict__ term_fac, int n_terms, const int8_t* __restrict__ band,
+                      const int* __restrict__ item_status, double* __restrict__ fom, int* __restrict__ cand_status) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  double acc = 0.0;
+  int worst = 0;
+  for (int f = 0; f < F; ++f) {
+    const int st = item_status[(size_t)c * F + f];
+    if (st < 0) worst = (worst < 0) ? min(worst, st) : st;
+    else if (worst >= 0) worst = max(worst, st);
+    const int b = band[f];
+    if (b < 0) continue;
+    const double2* s = S + ((size_t)c * F + f) * P * P;
+    for (int t = 0; t < n_terms; ++t) {
+      if (terms[t].band != b) continue;
+      const double2 v = s[terms[t].i * P + terms[t].j];
+      const double m2 = fmax(v.x * v.x + v.y * v.y, 1e-30);
+      acc += term_fac[t] * pow(m2, 0.5 * terms[t].power);
+    }
+  }
+  fom[c] = acc;
+  if (cand_status) cand_status[c] = worst;
+}
+
+__global__ void k_argmin(const double* __restrict__ fom, int C, int* __restrict__ out) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  const int tid = threadIdx.x;
+  double best = __builtin_inf();
+  int bi = 0x7fffffff;
+  for (int c = tid; c < C; c += 256) {
+    double v = fom[c];
+    if (v != v) v = __builtin_inf();
+    if (v < best || (v == best && c < bi)) best = v, bi = c;
+  }
+  sv[tid] = best;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double ov = sv[tid + s];
+      const int oi = si[tid + s];
+      if (ov < sv[tid] || (ov == sv[tid] && oi < si[tid])) sv[tid] = ov, si[tid] = oi;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *out = (si[0] == 0x7fffffff) ? 0 : si[0];
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_expand(hipStream_t s, const uint8_t* base, int n_cells, const int* off, const int* cells, int C,
+                         const int* cell_a, const int* cell_b, int M, int* Nc, int* Ilist) {
+  if (C <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand, dim3(C), dim3(256), (size_t)n_cells, s, base, n_cells, off, cells, cell_a, cell_b, M,
+                     Nc, Ilist);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(hipStream_t s, const int* Nc, int C, int* order) {
+  if (C <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_order, dim3((C + 255) / 256), dim3(256), 0, s, Nc, C, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(hipStream_t s, int* p, int n, int v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid) {
+  const int Q = rows_per_thread(p.nmax);
+  if (Q <= 1)
+    hipLaunchKernelGGL((k_eval_plain<1, 16>), dim3(grid), dim3(kThreads), 0, s, p);
+  else if (Q <= 2)
+    hipLaunchKernelGGL((k_eval_plain<2, 8>), dim3(grid), dim3(kThreads), 0, s, p);
+  else if (Q <= 4)
+    hipLaunchKernelGGL((k_eval_plain<4, 4>), dim3(grid), dim3(kThreads), 0, s, p);
+  else if (Q <= 8)
+    hipLaunchKernelGGL((k_eval_plain<8, 2>), dim3(grid), dim3(kThreads), 0, s, p);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_mixed(hipStream_t, const EvalParams&, int) { return hipErrorNotSupported; }
+
+hipError_t launch_fom(hipStream_t s, const double2* S, int C, int F, int P, const pxd_fom_term* terms,
+                      const double* term_fac, int n_terms, const int8_t* band, const int* item_status, double* fom,
+                      int* cand_status) {
+  if (C <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fom, dim3((C + 255) / 256), dim3(256), 0, s, S, C, F, P, terms, term_fac, n_terms, band,
+                     item_status, fom, cand_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_argmin(hipStream_t s, const double* fom, int C, int* argmin) {
+  hipLaunchKernelGGL(k_argmin, dim3(1), dim3(256), 0, s, fom, C, argmin);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(hipStream_t s, const double2* Zf, int M, const int* idx, int N, double2* out) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3(N), dim3(256), 0, s, Zf, M, idx, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_c64(hipStream_t s, const double2* in, float2* out, size_t n) {
+  hipLaunchKernelGGL(k_to_c64, dim3(4096), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace pxd

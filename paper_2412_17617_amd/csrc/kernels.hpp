@@ -1,0 +1,81 @@
+// Launch interface between the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "pxd.h"
+
+namespace pxd {
+
+// Everything one persistent evaluator launch needs.  All pointers are device
+// pointers.
+struct EvalParams {
+  const double2* Z128;  // F x M x M parent matrices (complex128)
+  const float2* Z64;    // F x M x M complex64 copy (mixed precision only)
+  int M, F, P, C;
+  const int* Nc;        // active size per candidate
+  const int* Ilist;     // C x M active indices, ascending
+  const int* order;     // candidates sorted by decreasing active size
+  const double* port_len;
+  double z0;
+  int n_items;          // items to process in this launch
+  const int* item_list; // explicit items (c * F + f), or null for the implicit frequency-major order
+  int* counter;         // persistent work counter (zeroed before the launch)
+  char* ws;             // workspace, one slot per workgroup
+  size_t slot_bytes;
+  int nmax;             // largest active size in the batch
+  double2* S;           // C x F x P x P
+  int* status;          // C x F
+  int* fb_list;         // mixed: items handed to the FP64 path
+  int* fb_count;
+  int* ir_iters;        // mixed: refinement iterations summed (one counter)
+  int ir_max;
+  double ir_tol;
+};
+
+// Per-slot layout of the workspace (byte offsets).
+struct SlotLayout {
+  size_t w_off, piv_off, x_off, bytes;
+  int ld;
+};
+
+// plain: complex128 N x (N + P) augmented system; mixed: complex64 N x N
+// factor, pivots and an FP64 solution block.
+__host__ __device__ inline SlotLayout slot_layout(int nmax, int P, bool mixed) {
+  SlotLayout s{};
+  auto up = [](size_t v, size_t a) -> size_t { return (v + a - 1) / a * a; };
+  if (!mixed) {
+    s.ld = (int)up(nmax + P, 4);
+    s.w_off = 0;
+    s.bytes = up((size_t)nmax * s.ld * 16, 256);
+  } else {
+    s.ld = (int)up(nmax, 4);
+    s.w_off = 0;
+    size_t w = up((size_t)nmax * s.ld * 8, 256);
+    s.piv_off = w;
+    size_t pv = up((size_t)nmax * 4, 256);
+    s.x_off = w + pv;
+    s.bytes = s.x_off + up((size_t)nmax * P * 16, 256);
+  }
+  return s;
+}
+
+// Rows of the register-resident sub-panel per thread for a given active size.
+__host__ __device__ inline int rows_per_thread(int nmax) { return (nmax + 255) / 256; }
+
+hipError_t launch_expand(hipStream_t s, const uint8_t* base, int n_cells, const int* off, const int* cells, int C,
+                         const int* cell_a, const int* cell_b, int M, int* Nc, int* Ilist);
+hipError_t launch_order(hipStream_t s, const int* Nc, int C, int* order);
+hipError_t launch_fill_int(hipStream_t s, int* p, int n, int v);
+hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid);
+hipError_t launch_eval_mixed(hipStream_t s, const EvalParams& p, int grid);
+hipError_t launch_fom(hipStream_t s, const double2* S, int C, int F, int P, const pxd_fom_term* terms,
+                      const double* term_fac, int n_terms, const int8_t* band, const int* item_status, double* fom,
+                      int* cand_status);
+hipError_t launch_argmin(hipStream_t s, const double* fom, int C, int* argmin);
+hipError_t launch_gather(hipStream_t s, const double2* Zf, int M, const int* idx, int N, double2* out);
+hipError_t launch_to_c64(hipStream_t s, const double2* in, float2* out, size_t n);
+
+}  // namespace pxd

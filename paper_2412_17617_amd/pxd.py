@@ -1,0 +1,259 @@
+"""Python binding of ``libpxd.so`` (ctypes).  Argument marshalling only.
+
+Every computation runs in the library: the structure builder and parent fill
+on the host (C++), everything else in the gfx950 kernels.  There is no Python
+or CPU fallback; if the library is missing the import fails.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpxd.so")
+
+OK, EINVAL, ENOMEM, ENOTLOADED, EDEVICE, ESHAPE = 0, -1, -2, -3, -4, -5
+PREC_FP64, PREC_MIXED32 = 0, 1
+KIND_ALWAYS, KIND_INNER, KIND_INTER, KIND_PIXPORT, KIND_VIA = 0, 1, 2, 3, 4
+STATUS_OK, STATUS_FALLBACK, STATUS_NONFINITE, STATUS_SINGULAR = 0, 1, -1, -2
+SIDES = {"right": 0, "top": 1, "left": 2, "bottom": 3}
+
+
+class PxdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pxd error {code}: {msg}")
+        self.code = code
+
+
+class Geometry(C.Structure):
+    _fields_ = [
+        ("n_layers", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("a", C.c_double), ("h", C.c_double), ("eps_r", C.c_double), ("tan_d", C.c_double),
+        ("n_ports", C.c_int32), ("port_side", C.POINTER(C.c_int32)), ("port_layer", C.POINTER(C.c_int32)),
+        ("n_vias", C.c_int32), ("via_x", C.POINTER(C.c_int32)), ("via_y", C.POINTER(C.c_int32)),
+    ]
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("device", C.c_int32), ("precision", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
+        ("wg_per_cu", C.c_int32), ("panel", C.c_int32),
+    ]
+
+
+class FomTerm(C.Structure):
+    _fields_ = [("band", C.c_int32), ("i", C.c_int32), ("j", C.c_int32), ("log10_factor", C.c_double),
+                ("power", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("items", C.c_int64), ("fallbacks", C.c_int64), ("ir_iterations", C.c_int64),
+        ("max_active", C.c_int32), ("min_active", C.c_int32),
+        ("ms_expand", C.c_double), ("ms_solve", C.c_double), ("ms_fallback", C.c_double), ("ms_fom", C.c_double),
+    ]
+
+
+_VP = C.c_void_p
+_SIGS = {
+    "pxd_problem_create": (C.c_int, [C.POINTER(Geometry), C.POINTER(_VP)]),
+    "pxd_problem_destroy": (None, [_VP]),
+    "pxd_problem_sizes": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pxd_problem_classification": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "pxd_problem_fill": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32]),
+    "pxd_create": (C.c_int, [C.POINTER(Options), C.POINTER(_VP)]),
+    "pxd_destroy": (None, [_VP]),
+    "pxd_last_error": (C.c_char_p, [_VP]),
+    "pxd_load_parent": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP]),
+    "pxd_load_map": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_double]),
+    "pxd_set_fom": (C.c_int, [_VP, C.c_int32, _VP, _VP]),
+    "pxd_set_fom_paper": (C.c_int, [_VP]),
+    "pxd_evaluate_flips": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "pxd_evaluate_flips_device": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "pxd_expand": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "pxd_gather": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP]),
+    "pxd_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
+}
+
+_lib_handle = None
+
+
+def lib():
+    """Load libpxd.so (built by ``python -m paper_2412_17617_amd.build``)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2412_17617_amd.build")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib_handle = h
+    return _lib_handle
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_VP)
+
+
+def _check(rc, ctx=None):
+    if rc != OK:
+        msg = lib().pxd_last_error(ctx)
+        raise PxdError(rc, msg.decode() if msg else "")
+
+
+class Problem:
+    """Mesh + RWG classification + host EFIE fill of one workload geometry."""
+
+    def __init__(self, n_layers, nx, ny, a, h, eps_r, tan_d, ports, vias=()):
+        L = lib()
+        self._keep = [
+            np.array([SIDES[s] if isinstance(s, str) else int(s) for s, _ in ports] or [0], dtype=np.int32),
+            np.array([l for _, l in ports] or [0], dtype=np.int32),
+            np.array([x for x, _ in vias] or [0], dtype=np.int32),
+            np.array([y for _, y in vias] or [0], dtype=np.int32),
+        ]
+        g = Geometry(n_layers, nx, ny, a, h, eps_r, tan_d, len(ports),
+                     self._keep[0].ctypes.data_as(C.POINTER(C.c_int32)),
+                     self._keep[1].ctypes.data_as(C.POINTER(C.c_int32)), len(vias),
+                     self._keep[2].ctypes.data_as(C.POINTER(C.c_int32)),
+                     self._keep[3].ctypes.data_as(C.POINTER(C.c_int32)))
+        h_ = _VP()
+        _check(L.pxd_problem_create(C.byref(g), C.byref(h_)))
+        self._h = h_
+        M, nc, npo = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(L.pxd_problem_sizes(self._h, C.byref(M), C.byref(nc), C.byref(npo)))
+        self.M, self.n_cells, self.n_ports = M.value, nc.value, npo.value
+
+    @classmethod
+    def from_spec(cls, spec):
+        """Build from any object with the workload attributes (n_layers, nx, ny,
+        a, h, eps_r, tan_d, ports with .side/.layer, via_sites())."""
+        return cls(spec.n_layers, spec.nx, spec.ny, spec.a, spec.h, spec.eps_r, spec.tan_d,
+                   [(p.side, p.layer) for p in spec.ports], list(spec.via_sites()))
+
+    def classification(self):
+        kind = np.zeros(self.M, np.uint8)
+        ca = np.zeros(self.M, np.int32)
+        cb = np.zeros(self.M, np.int32)
+        pbf = np.zeros(self.n_ports, np.int32)
+        plen = np.zeros(self.n_ports, np.float64)
+        _check(lib().pxd_problem_classification(self._h, _ptr(kind), _ptr(ca), _ptr(cb), _ptr(pbf), _ptr(plen)))
+        return kind, ca, cb, pbf, plen
+
+    def fill(self, freqs, n_threads=0, out=None):
+        freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+        Z = out if out is not None else np.empty((len(freqs), self.M, self.M), np.complex128)
+        assert Z.shape == (len(freqs), self.M, self.M) and Z.dtype == np.complex128 and Z.flags.c_contiguous
+        _check(lib().pxd_problem_fill(self._h, len(freqs), _ptr(freqs), _ptr(Z), n_threads))
+        return Z
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib_handle is not None:
+            _lib_handle.pxd_problem_destroy(self._h)
+            self._h = None
+
+
+class Evaluator:
+    """GPU evaluator context (one per device and host thread)."""
+
+    def __init__(self, device=0, precision=PREC_FP64, ir_max_iter=10, ir_tol=1e-10, wg_per_cu=0, panel=0):
+        o = Options(device, precision, ir_max_iter, ir_tol, wg_per_cu, panel)
+        h_ = _VP()
+        _check(lib().pxd_create(C.byref(o), C.byref(h_)))
+        self._h = h_
+        self.M = self.F = self.P = self.n_cells = 0
+
+    def _c(self, rc):
+        _check(rc, self._h)
+
+    def load_parent(self, Z, freqs):
+        Z = np.ascontiguousarray(Z, dtype=np.complex128)
+        freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+        F, M, M2 = Z.shape
+        assert M == M2 and F == len(freqs)
+        self._c(lib().pxd_load_parent(self._h, M, F, _ptr(freqs), _ptr(Z)))
+        self.M, self.F = M, F
+
+    def load_map(self, n_cells, kind, cell_a, cell_b, port_bf, port_len, z0=50.0):
+        kind = np.ascontiguousarray(kind, np.uint8)
+        ca = np.ascontiguousarray(cell_a, np.int32)
+        cb = np.ascontiguousarray(cell_b, np.int32)
+        pbf = np.ascontiguousarray(port_bf, np.int32)
+        pl = np.ascontiguousarray(port_len, np.float64)
+        self._c(lib().pxd_load_map(self._h, n_cells, len(ca), _ptr(kind), _ptr(ca), _ptr(cb), len(pbf), _ptr(pbf),
+                                   _ptr(pl), z0))
+        self.n_cells, self.P, self.M = n_cells, len(pbf), len(ca)
+
+    def load_problem(self, problem: Problem, z0=50.0):
+        kind, ca, cb, pbf, pl = problem.classification()
+        self.load_map(problem.n_cells, kind, ca, cb, pbf, pl, z0)
+
+    def set_fom_paper(self):
+        self._c(lib().pxd_set_fom_paper(self._h))
+
+    def set_fom(self, terms, band_of_freq):
+        arr = (FomTerm * max(1, len(terms)))(*[FomTerm(*t) for t in terms])
+        band = np.ascontiguousarray(band_of_freq, np.int8)
+        self._c(lib().pxd_set_fom(self._h, len(terms), C.cast(arr, _VP), _ptr(band)))
+
+    def evaluate_flips(self, base_map, offsets, cells, want_S=True):
+        base = np.ascontiguousarray(base_map, np.uint8)
+        off = np.ascontiguousarray(offsets, np.int32)
+        cl = np.ascontiguousarray(cells, np.int32)
+        n = len(off) - 1
+        S = np.empty((n, self.F, self.P, self.P), np.complex128) if want_S else None
+        fom = np.empty(n, np.float64)
+        st = np.empty(n, np.int32)
+        am = np.zeros(1, np.int32)
+        self._c(lib().pxd_evaluate_flips(self._h, _ptr(base), n, _ptr(off), _ptr(cl if len(cl) else
+                                         np.zeros(1, np.int32)), _ptr(S), _ptr(fom), _ptr(st), _ptr(am)))
+        return S, fom, st, int(am[0])
+
+    def evaluate_flips_device(self, stream, base_map, offsets, cells, S_out, fom_out, status_out=None,
+                              argmin_out=None):
+        """All arrays are torch CUDA tensors (or objects with data_ptr());
+        stream is a torch.cuda.Stream or a raw hipStream_t integer."""
+        sp = getattr(stream, "cuda_stream", stream)
+
+        def dp(t):
+            return None if t is None else _VP(t.data_ptr())
+
+        n = offsets.numel() - 1
+        self._c(lib().pxd_evaluate_flips_device(self._h, _VP(sp), dp(base_map), n, dp(offsets), dp(cells),
+                                                cells.numel(), dp(S_out), dp(fom_out), dp(status_out),
+                                                dp(argmin_out)))
+
+    def expand(self, base_map, offsets, cells):
+        base = np.ascontiguousarray(base_map, np.uint8)
+        off = np.ascontiguousarray(offsets, np.int32)
+        cl = np.ascontiguousarray(cells, np.int32)
+        n = len(off) - 1
+        N = np.empty(n, np.int32)
+        idx = np.empty((n, self.M), np.int32)
+        self._c(lib().pxd_expand(self._h, _ptr(base), n, _ptr(off), _ptr(cl if len(cl) else np.zeros(1, np.int32)),
+                                 _ptr(N), _ptr(idx)))
+        return N, [idx[c, :N[c]].copy() for c in range(n)]
+
+    def gather(self, f, idx):
+        idx = np.ascontiguousarray(idx, np.int32)
+        out = np.empty((len(idx), len(idx)), np.complex128)
+        self._c(lib().pxd_gather(self._h, f, len(idx), _ptr(idx), _ptr(out)))
+        return out
+
+    def stats(self):
+        s = Stats()
+        self._c(lib().pxd_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib_handle is not None:
+            _lib_handle.pxd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,86 @@
+"""The C ABI library loads, exports what include/pxd.h declares, rejects bad
+arguments, and its host-side structure builder and parent fill agree with the
+oracle's independent implementations.  No GPU calls."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import efie, geometry
+from synth import get_spec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+pxd = pytest.importorskip("paper_2412_17617_amd.pxd")
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "pxd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pxd_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = C.CDLL(pxd.LIB_PATH)
+    syms = header_symbols()
+    assert len(syms) >= 17
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert missing == []
+    # the binding knows every entry point
+    assert set(syms) <= set(pxd._SIGS)
+
+
+@pytest.mark.parametrize("name", ["plain8", "tiny4x2", "small6x3", "batched20", "stress24"])
+def test_structure_matches_oracle(name):
+    spec = get_spec(name)
+    pb = pxd.Problem.from_spec(spec)
+    st = geometry.build_structure(spec)
+    assert pb.M == st.M and pb.n_cells == spec.n_cells and pb.n_ports == len(spec.ports)
+    kind, ca, cb, pbf, plen = pb.classification()
+    assert [int(k) for k in kind] == [b.kind for b in st.bfs]
+    assert all(tuple(int(c) for c in (ca[i], cb[i]) if c >= 0) == tuple(b.cells) for i, b in enumerate(st.bfs))
+    assert list(pbf) == st.port_bf
+    length, _, _ = geometry.rwg_geometry(st)
+    assert np.array_equal(plen, length[st.port_bf])
+
+
+@pytest.mark.parametrize("name", ["plain8", "tiny4x2", "small6x3"])
+def test_host_fill_matches_oracle_fill(name):
+    """Two independent implementations of the same discretisation."""
+    spec = get_spec(name)
+    pb = pxd.Problem.from_spec(spec)
+    st = geometry.build_structure(spec)
+    freqs = spec.freqs[[0, -1]]
+    Z = pb.fill(freqs, n_threads=4)
+    Zo = np.stack([efie.fill(st, f) for f in freqs])
+    assert np.array_equal(Z, np.transpose(Z, (0, 2, 1)))
+    assert np.abs(Z - Zo).max() <= 1e-12 * np.abs(Zo).max()
+
+
+def test_bad_geometry_is_rejected():
+    with pytest.raises(pxd.PxdError) as e:
+        pxd.Problem(1, 0, 4, 1e-3, 0.0, 1.0, 0.0, [("right", 0)])
+    assert e.value.code == pxd.EINVAL
+    with pytest.raises(pxd.PxdError):
+        pxd.Problem(1, 4, 4, 1e-3, 0.0, 1.0, 0.0, [("right", 3)])  # port on a missing layer
+    with pytest.raises(pxd.PxdError):
+        pxd.Problem(1, 4, 4, 1e-3, 0.0, 1.0, 0.0, [("right", 0)], vias=[(1, 1)])  # via needs two layers
+
+
+def test_null_arguments_return_codes():
+    lib = pxd.lib()
+    assert lib.pxd_problem_create(None, None) == pxd.EINVAL
+    assert lib.pxd_problem_sizes(None, None, None, None) == pxd.EINVAL
+    assert lib.pxd_problem_fill(None, 1, None, None, 1) == pxd.EINVAL
+    assert lib.pxd_create(None, None) == pxd.EINVAL
+    assert lib.pxd_load_parent(None, 1, 1, None, None) == pxd.EINVAL
+    assert lib.pxd_get_stats(None, None) == pxd.EINVAL
+    assert b"NULL" in lib.pxd_last_error(None) or lib.pxd_last_error(None)
+
+
+def test_fill_rejects_bad_sizes():
+    pb = pxd.Problem.from_spec(get_spec("tiny3"))
+    rc = pxd.lib().pxd_problem_fill(pb._h, 0, None, None, 1)
+    assert rc == pxd.EINVAL
