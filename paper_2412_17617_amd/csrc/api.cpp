@@ -62,6 +62,7 @@ struct pxd_ctx {
   DevBuf base, off, cells, Nc, Ilist, order, counter, S, item_status, cand_status, fom, argmin, ws, fb_list;
   std::vector<int> hNc;
   pxd_stats stats{};
+  bool stats_pending_counts = false;
 
   int fail(int rc, const std::string& m) {
     err = m;
@@ -93,7 +94,7 @@ int evaluate(pxd_ctx* ctx, hipStream_t s, const uint8_t* d_base, int C, const in
   HIPCHK(ctx, ctx->Nc.ensure(sizeof(int) * C));
   HIPCHK(ctx, ctx->Ilist.ensure(sizeof(int) * (size_t)C * M));
   HIPCHK(ctx, ctx->order.ensure(sizeof(int) * C));
-  HIPCHK(ctx, ctx->counter.ensure(sizeof(int) * 4));
+  HIPCHK(ctx, ctx->counter.ensure(sizeof(int) * 8));
   HIPCHK(ctx, ctx->item_status.ensure(sizeof(int) * (size_t)C * F));
   HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
   HIPCHK(ctx, pxd::launch_expand(s, d_base, ctx->n_cells, d_off, d_cells, C, ctx->cell_a.as<int>(),
@@ -112,8 +113,12 @@ int evaluate(pxd_ctx* ctx, hipStream_t s, const uint8_t* d_base, int C, const in
   const int wg_per_cu = ctx->opt.wg_per_cu > 0 ? ctx->opt.wg_per_cu : 2;
   const long long items = (long long)C * F;
   int grid = (int)std::min<long long>(items, (long long)ctx->n_cu * wg_per_cu);
-  pxd::SlotLayout lay = pxd::slot_layout(nmax, P, mixed);
-  HIPCHK(ctx, ctx->ws.ensure(lay.bytes * (size_t)grid));
+  const pxd::SlotLayout lay_p = pxd::slot_layout(nmax, P, false);
+  const pxd::SlotLayout lay_m = pxd::slot_layout(nmax, P, true);
+  // the mixed path re-solves unrefined items with the FP64 kernel in the same slots
+  const size_t slot = mixed ? std::max(lay_p.bytes, lay_m.bytes) : lay_p.bytes;
+  HIPCHK(ctx, ctx->ws.ensure(slot * (size_t)grid));
+  if (mixed) HIPCHK(ctx, ctx->fb_list.ensure(sizeof(int) * (size_t)items));
 
   pxd::EvalParams ep{};
   ep.Z128 = ctx->Z128.as<double2>();
@@ -128,20 +133,34 @@ int evaluate(pxd_ctx* ctx, hipStream_t s, const uint8_t* d_base, int C, const in
   ep.item_list = nullptr;
   ep.counter = ctx->counter.as<int>();
   ep.ws = ctx->ws.as<char>();
-  ep.slot_bytes = lay.bytes;
+  ep.slot_bytes = slot;
+  ep.ld = mixed ? lay_m.ld : lay_p.ld;
   ep.nmax = nmax;
   ep.S = d_S;
   ep.status = ctx->item_status.as<int>();
   ep.ir_max = ctx->opt.ir_max_iter;
   ep.ir_tol = ctx->opt.ir_tol;
-  HIPCHK(ctx, pxd::launch_fill_int(s, ep.counter, 4, 0));
+  int* cnt = ctx->counter.as<int>();  // [0] work, [1] fallback count, [2] refinement steps, [3] fallback work
+  ep.fb_list = ctx->fb_list.as<int>();
+  ep.fb_count = cnt + 1;
+  ep.ir_iters = cnt + 2;
+  HIPCHK(ctx, pxd::launch_fill_int(s, cnt, 8, 0));
   if (!mixed) {
     HIPCHK(ctx, pxd::launch_eval_plain(s, ep, grid));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
   } else {
     HIPCHK(ctx, pxd::launch_eval_mixed(s, ep, grid));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    pxd::EvalParams fb = ep;  // FP64 re-solve of the items refinement could not settle
+    fb.item_list = ep.fb_list;
+    fb.n_items_dev = cnt + 1;
+    fb.counter = cnt + 3;
+    fb.ld = lay_p.ld;
+    fb.fallback_mode = 1;
+    HIPCHK(ctx, pxd::launch_eval_plain(s, fb, grid));
+    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
   }
-  HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
-  HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
   HIPCHK(ctx, pxd::launch_fom(s, d_S, C, F, P, ctx->terms.as<pxd_fom_term>(), ctx->term_fac.as<double>(),
                               ctx->n_terms, ctx->band.as<int8_t>(), ctx->item_status.as<int>(), d_fom,
                               d_cand_status));
@@ -150,6 +169,7 @@ int evaluate(pxd_ctx* ctx, hipStream_t s, const uint8_t* d_base, int C, const in
   ctx->stats.items = items;
   ctx->stats.max_active = nmax;
   ctx->stats.min_active = nmin;
+  ctx->stats_pending_counts = mixed;
   return PXD_OK;
 }
 
@@ -177,7 +197,7 @@ int pxd_create(const pxd_options* opt, pxd_ctx** out) {
   if (!ctx) return pxd::set_thread_error(PXD_ENOMEM, "out of host memory");
   if (opt) ctx->opt = *opt;
   if (ctx->opt.ir_max_iter <= 0) ctx->opt.ir_max_iter = 10;
-  if (!(ctx->opt.ir_tol > 0)) ctx->opt.ir_tol = 1e-10;
+  if (!(ctx->opt.ir_tol > 0)) ctx->opt.ir_tol = 1e-7;
   if (ctx->opt.precision != PXD_PREC_FP64 && ctx->opt.precision != PXD_PREC_MIXED32) {
     delete ctx;
     return pxd::set_thread_error(PXD_EINVAL, "unknown precision mode");
@@ -437,6 +457,15 @@ int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out) {
     if (hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]) == hipSuccess) out->ms_expand = a;
     if (hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]) == hipSuccess) out->ms_solve = b;
     if (hipEventElapsedTime(&c, ctx->ev[3], ctx->ev[4]) == hipSuccess) out->ms_fom = c;
+    float d = 0;
+    if (ctx->stats_pending_counts && hipEventElapsedTime(&d, ctx->ev[2], ctx->ev[3]) == hipSuccess) {
+      out->ms_fallback = d;
+      int h[4] = {0, 0, 0, 0};
+      if (hipMemcpy(h, ctx->counter.p, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
+        out->fallbacks = h[1];
+        out->ir_iterations = h[2];
+      }
+    }
   }
   return PXD_OK;
 }

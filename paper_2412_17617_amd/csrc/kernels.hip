@@ -368,80 +368,106 @@ __device__ __forceinline__ void swap_trsm(typename Cx<R>::T* __restrict__ W, int
 }
 
 // A22 -= L21 U12 on rows [k + kb, N), columns [k + kb, ncols).
+// Wave w owns block rows w, w + 4, ... of 32 rows and keeps their (negated)
+// L21 fragments in registers while sweeping the block columns; the four waves
+// sweep the columns in the same order, so a U12 block is fetched from memory
+// once and served to the other waves from cache.  Each 32 x 32 output tile
+// issues its loads (C into the accumulators, the U12 fragments) before its
+// 128 MFMAs, so the two waves sharing a SIMD overlap one tile's memory
+// latency with the other's arithmetic.
 template <typename R>
-__device__ __forceinline__ void trailing_update(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int N, int ncols) {
+__device__ __forceinline__ void trailing_update(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int N,
+                                                int ncols) {
   using T = typename Cx<R>::T;
   using MF = Mfma<R>;
   using acc_t = typename MF::acc_t;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
   const int r0 = k + kb, c0 = k + kb;
   const int mr = N - r0, nc = ncols - c0;
   if (mr <= 0 || nc <= 0) return;
   const int tmn = (mr + 31) >> 5, tnn = (nc + 31) >> 5;
-  const int nt = tmn * tnn;
-  const int per = (nt + kWaves - 1) / kWaves;
-  const int t0 = wid * per, t1 = min(nt, t0 + per);
-  const int kqn = (kb + 3) >> 2;
-  int cur = -1;
-  T afr[2][NB / 4];
-  for (int t = t0; t < t1; ++t) {
-    const int tm = t / tnn, tn = t - tm * tnn;
-    if (tm != cur) {
-      cur = tm;
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int kq = 0; kq < NB / 4; ++kq) {
-          const int r = r0 + 32 * tm + 16 * a + (lane & 15);
-          const int kk = 4 * kq + (lane >> 4);
-          afr[a][kq] = (r < N && kk < kb) ? W[(size_t)r * ld + k + kk] : T{0, 0};
-        }
-    }
-    acc_t cr[2][2], ci[2][2];
+  for (int tm = wid; tm < tmn; tm += kWaves) {
+    // -L21 fragments of this block row: A operand lane l holds row l % 16, k l / 16
+    R anr[2][NB / 4], ani[2][NB / 4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cr[a][b] = acc_t{0, 0, 0, 0};
-        ci[a][b] = acc_t{0, 0, 0, 0};
+      for (int kq = 0; kq < NB / 4; ++kq) {
+        const int r = r0 + 32 * tm + 16 * a + l16;
+        const int kk = 4 * kq + lk;
+        const T v = (r < N && kk < kb) ? W[(size_t)r * ld + k + kk] : T{0, 0};
+        anr[a][kq] = -v.x;
+        ani[a][kq] = -v.y;
       }
+    for (int tn = 0; tn < tnn; ++tn) {
+      acc_t cr[2][2], ci[2][2];
 #pragma unroll
-    for (int kq = 0; kq < NB / 4; ++kq) {
-      if (kq < kqn) {
-        T bfr[2];
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int kk = 4 * kq + (lane >> 4);
-          const int col = c0 + 32 * tn + 16 * b + (lane & 15);
-          bfr[b] = (kk < kb && col < ncols) ? W[(size_t)(k + kk) * ld + col] : T{0, 0};
-        }
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = r0 + 32 * tm + 16 * a + MF::row(lane, i);
+            const int col = c0 + 32 * tn + 16 * b + l16;
+            const T v = (r < N && col < ncols) ? W[(size_t)r * ld + col] : T{0, 0};
+            cr[a][b][i] = v.x;
+            ci[a][b][i] = v.y;
+          }
+      auto load_b = [&](int kq, int b) -> T {
+        const int kk = 4 * kq + lk;
+        const int col = c0 + 32 * tn + 16 * b + l16;
+        return (kk < kb && col < ncols) ? W[(size_t)(k + kk) * ld + col] : T{0, 0};
+      };
+      // C -= A B:  Cr += (-Ar) Br + (-Ai)(-Bi),  Ci += (-Ar) Bi + (-Ai) Br
+      auto mma = [&](int kq, const T (&bq)[2]) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
-            cr[a][b] = MF::run(afr[a][kq].x, bfr[b].x, cr[a][b]);
-            cr[a][b] = MF::run(-afr[a][kq].y, bfr[b].y, cr[a][b]);
-            ci[a][b] = MF::run(afr[a][kq].x, bfr[b].y, ci[a][b]);
-            ci[a][b] = MF::run(afr[a][kq].y, bfr[b].x, ci[a][b]);
+            cr[a][b] = MF::run(anr[a][kq], bq[b].x, cr[a][b]);
+            cr[a][b] = MF::run(ani[a][kq], -bq[b].y, cr[a][b]);
+            ci[a][b] = MF::run(anr[a][kq], bq[b].y, ci[a][b]);
+            ci[a][b] = MF::run(ani[a][kq], bq[b].x, ci[a][b]);
           }
-      }
-    }
+      };
+      if constexpr (sizeof(R) == 4) {
+        // complex64: every U12 fragment of the tile in flight at once
+        T bfr[NB / 4][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int kq = 0; kq < NB / 4; ++kq)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+          for (int b = 0; b < 2; ++b) bfr[kq][b] = load_b(kq, b);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = r0 + 32 * tm + 16 * a + MF::row(lane, i);
-          const int col = c0 + 32 * tn + 16 * b + (lane & 15);
-          if (r < N && col < ncols) {
-            T* q = W + (size_t)r * ld + col;
-            T v = *q;
-            v.x -= cr[a][b][i];
-            v.y -= ci[a][b][i];
-            *q = v;
+        for (int kq = 0; kq < NB / 4; ++kq) mma(kq, bfr[kq]);
+      } else {
+        // complex128: stream the fragments one k-step ahead (register budget)
+        T cur[2] = {load_b(0, 0), load_b(0, 1)};
+#pragma unroll
+        for (int kq = 0; kq < NB / 4; ++kq) {
+          T nxt[2];
+          if (kq + 1 < NB / 4) {
+            nxt[0] = load_b(kq + 1, 0);
+            nxt[1] = load_b(kq + 1, 1);
+          }
+          mma(kq, cur);
+          if (kq + 1 < NB / 4) {
+            cur[0] = nxt[0];
+            cur[1] = nxt[1];
           }
         }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = r0 + 32 * tm + 16 * a + MF::row(lane, i);
+            const int col = c0 + 32 * tn + 16 * b + l16;
+            if (r < N && col < ncols) W[(size_t)r * ld + col] = T{cr[a][b][i], ci[a][b][i]};
+          }
+    }
   }
 }
 
@@ -525,14 +551,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_plain(EvalParams p) {
   __shared__ int sI[kThreads * Q];
   __shared__ int s_item;
   const int tid = threadIdx.x;
-  const int ld = slot_layout(p.nmax, p.P, false).ld;
+  const int ld = p.ld;
+  const int n_items = p.n_items_dev ? *p.n_items_dev : p.n_items;
   T* W = reinterpret_cast<T*>(p.ws + (size_t)blockIdx.x * p.slot_bytes);
   for (;;) {
     if (tid == 0) s_item = atomicAdd(p.counter, 1);
     __syncthreads();
     const int it = s_item;
     __syncthreads();
-    if (it >= p.n_items) break;
+    if (it >= n_items) break;
     int c, f;
     if (p.item_list) {
       const int e = p.item_list[it];
@@ -556,11 +583,296 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_plain(EvalParams p) {
     int st = port_solve_and_s(W, ld, N, p.P, p.port_len, p.z0, Sout);
     if (tid == 0) {
       if (sm.bad && st == PXD_STATUS_OK) st = PXD_STATUS_SINGULAR;
+      if (p.fallback_mode && st == PXD_STATUS_OK) st = PXD_STATUS_FALLBACK;
       p.status[(size_t)c * p.F + f] = st;
     }
     __syncthreads();
   }
 }
+
+
+// ------------------------------------------------------------------ mixed precision
+
+// out[jr] -= sum_j row[j] y[j * P + jr] for j < kb (kb <= NB), jr < P: the
+// row segment is read with unrolled 16-byte loads issued back to back.
+__device__ __forceinline__ void rows_update(const float2* __restrict__ row, int kb, const float2* y, float2* out,
+                                            int P) {
+  float4 seg[NB / 2];
+  const float4* r4 = reinterpret_cast<const float4*>(row);
+  const bool aligned = (reinterpret_cast<uintptr_t>(row) & 15) == 0;
+#pragma unroll
+  for (int q = 0; q < NB / 2; ++q) {
+    if (2 * q + 1 < kb && aligned) {
+      seg[q] = r4[q];
+    } else {
+      const float2 lo = (2 * q < kb) ? row[2 * q] : float2{0, 0};
+      const float2 hi = (2 * q + 1 < kb) ? row[2 * q + 1] : float2{0, 0};
+      seg[q] = float4{lo.x, lo.y, hi.x, hi.y};
+    }
+  }
+  float2 acc[4] = {};
+#pragma unroll
+  for (int jr = 0; jr < 4; ++jr)
+    if (jr < P) acc[jr] = out[jr];
+#pragma unroll
+  for (int q = 0; q < NB / 2; ++q) {
+    const float2 l0 = float2{seg[q].x, seg[q].y}, l1 = float2{seg[q].z, seg[q].w};
+#pragma unroll
+    for (int jr = 0; jr < 4; ++jr)
+      if (jr < P) {
+        if (2 * q < kb) acc[jr] = cfms(acc[jr], l0, y[(2 * q) * P + jr]);
+        if (2 * q + 1 < kb) acc[jr] = cfms(acc[jr], l1, y[(2 * q + 1) * P + jr]);
+      }
+  }
+#pragma unroll
+  for (int jr = 0; jr < 4; ++jr)
+    if (jr < P) out[jr] = acc[jr];
+}
+
+// Solve (L U) x = P b in complex64 for the P right-hand sides held in LDS
+// (b[row * P + j]), using the factor in W (unit-lower L below the diagonal,
+// U on and above) and the per-panel pivots.  Interchanges were applied only
+// to the panel and trailing columns during the factorisation, so they are
+// replayed panel by panel between the block updates.
+__device__ __forceinline__ void lu_solve_c64(const float2* __restrict__ W, int ld, int N, const int* __restrict__ piv,
+                                             float2* b, int P) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // forward: b <- L^-1 P b
+  for (int k = 0; k < N; k += NB) {
+    const int kb = min(NB, N - k);
+    if (tid < P)
+      for (int i = 0; i < kb; ++i) {
+        const int r = k + i, q = piv[r];
+        if (q != r) {
+          const float2 t = b[r * P + tid];
+          b[r * P + tid] = b[q * P + tid];
+          b[q * P + tid] = t;
+        }
+      }
+    __syncthreads();
+    if (wid == 0) {
+      float2 l[NB];
+      const bool mine = lane < kb;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) l[j] = (mine && j < lane) ? W[(size_t)(k + lane) * ld + k + j] : float2{0, 0};
+      for (int jr = 0; jr < P; ++jr) {
+        float2 v = mine ? b[(k + lane) * P + jr] : float2{0, 0};
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const float2 bj = float2{__shfl(v.x, j, 64), __shfl(v.y, j, 64)};
+          if (j < lane) v = cfms(v, l[j], bj);
+        }
+        if (mine) b[(k + lane) * P + jr] = v;
+      }
+    }
+    __syncthreads();
+    for (int r = k + kb + tid; r < N; r += kThreads) rows_update(W + (size_t)r * ld + k, kb, b + (size_t)k * P, b + (size_t)r * P, P);
+    __syncthreads();
+  }
+  // backward: b <- U^-1 b
+  const int nblk = (N + NB - 1) / NB;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int k = bi * NB, kb = min(NB, N - k);
+    if (wid == 0) {
+      float2 u[NB];
+      const bool mine = lane < kb;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) u[j] = (mine && j >= lane && j < kb) ? W[(size_t)(k + lane) * ld + k + j] : float2{0, 0};
+      float2 diag = float2{1, 0};
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j == lane) diag = u[j];
+      const float2 rdiag = crecip(diag);
+      for (int jr = 0; jr < P; ++jr) {
+        float2 v = mine ? b[(k + lane) * P + jr] : float2{0, 0};
+#pragma unroll
+        for (int j = NB - 1; j >= 0; --j) {
+          if (j < kb) {
+            // row j is final once the columns right of it are eliminated
+            float2 xj = cmul(v, rdiag);
+            xj = float2{__shfl(xj.x, j, 64), __shfl(xj.y, j, 64)};
+            if (lane == j) v = xj;
+            else if (lane < j) v = cfms(v, u[j], xj);
+          }
+        }
+        if (mine) b[(k + lane) * P + jr] = v;
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < k; r += kThreads) rows_update(W + (size_t)r * ld + k, kb, b + (size_t)k * P, b + (size_t)r * P, P);
+    __syncthreads();
+  }
+}
+
+// r = V - Z_A x in FP64, Z_A gathered on the fly from the complex128 parent
+// (with the Z0 loads of the port functions); the result, rounded to
+// complex64, replaces b.  Sixteen lanes per row (four rows per wave), each
+// lane keeping four independent gathers in flight.
+__device__ __forceinline__ void residual_fp64(const double2* __restrict__ Zf, int M, const int* sI, int N, int P,
+                                              const double* __restrict__ plen, double z0,
+                                              const double2* __restrict__ x, float2* b) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int sub = lane >> 4, l16 = lane & 15;
+  for (int i0 = 4 * wid; i0 < N; i0 += 4 * kWaves) {
+    const int i = i0 + sub;
+    double2 acc[4] = {};
+    if (i < N) {
+      const double2* zrow = Zf + (size_t)sI[i] * M;
+      int j = l16;
+      for (; j + 48 < N; j += 64) {
+        double2 z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = zrow[sI[j + 16 * u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int jr = 0; jr < 4; ++jr)
+            if (jr < P) {
+              const double2 xv = x[(size_t)(j + 16 * u) * P + jr];
+              acc[jr].x += z[u].x * xv.x - z[u].y * xv.y;
+              acc[jr].y += z[u].x * xv.y + z[u].y * xv.x;
+            }
+      }
+      for (; j < N; j += 16) {
+        const double2 zv = zrow[sI[j]];
+#pragma unroll
+        for (int jr = 0; jr < 4; ++jr)
+          if (jr < P) {
+            const double2 xv = x[(size_t)j * P + jr];
+            acc[jr].x += zv.x * xv.x - zv.y * xv.y;
+            acc[jr].y += zv.x * xv.y + zv.y * xv.x;
+          }
+      }
+    }
+#pragma unroll
+    for (int jr = 0; jr < 4; ++jr) {
+#pragma unroll
+      for (int off = 8; off >= 1; off >>= 1) {
+        acc[jr].x += __shfl_xor(acc[jr].x, off, 16);
+        acc[jr].y += __shfl_xor(acc[jr].y, off, 16);
+      }
+    }
+    if (i < N && l16 < P) {
+      const int jr = l16;
+      double2 a = acc[0];
+#pragma unroll
+      for (int t = 1; t < 4; ++t)
+        if (t == jr) a = acc[t];
+      const int pi = i - (N - P);  // port index of this row, if it is a port row
+      double2 r = double2{-a.x, -a.y};
+      if (pi >= 0) {
+        const double2 xv = x[(size_t)i * P + jr];
+        const double load = z0 * plen[pi] * plen[pi];
+        r.x -= load * xv.x;
+        r.y -= load * xv.y;
+        if (pi == jr) r.x += plen[pi];  // V: 1 V source EMF in the gap of port jr
+      }
+      b[i * P + jr] = float2{(float)r.x, (float)r.y};
+    }
+  }
+  __syncthreads();
+}
+
+// Mixed precision item: complex64 LU of Z_A, initial complex64 solve, then
+// refinement with FP64 residuals until every port current's correction is
+// below ir_tol relative to it.  Items that do not converge are queued for the
+// FP64 path.
+template <int Q, int SB>
+__global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
+  using T = float2;
+  __shared__ LuShared<float> sm;
+  __shared__ int s_item, s_conv;
+  extern __shared__ char dyn[];
+  int* sI = reinterpret_cast<int*>(dyn);
+  float2* b = reinterpret_cast<float2*>(dyn + ((size_t)p.nmax * 4 + 15) / 16 * 16);
+  const int tid = threadIdx.x;
+  const int ld = p.ld;
+  const SlotLayout lay = slot_layout(p.nmax, p.P, true);
+  char* slot = p.ws + (size_t)blockIdx.x * p.slot_bytes;
+  T* W = reinterpret_cast<T*>(slot + lay.w_off);
+  int* piv = reinterpret_cast<int*>(slot + lay.piv_off);
+  double2* x = reinterpret_cast<double2*>(slot + lay.x_off);
+  const int P = p.P;
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(p.counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= p.n_items) break;
+    const int f = it / p.C;
+    const int c = p.order[it - f * p.C];
+    const int N = p.Nc[c];
+    double2* Sout = p.S + ((size_t)c * p.F + f) * P * P;
+    if (N > kThreads * Q || N > p.nmax || N < P) {
+      if (tid == 0) p.status[(size_t)c * p.F + f] = PXD_STATUS_NONFINITE;
+      continue;
+    }
+    for (int s = tid; s < N; s += kThreads) sI[s] = p.Ilist[(size_t)c * p.M + s];
+    if (tid == 0) sm.bad = 0;
+    __syncthreads();
+    const double2* Zf128 = p.Z128 + (size_t)f * p.M * p.M;
+    gather_item<T, float2>(W, ld, p.Z64 + (size_t)f * p.M * p.M, p.M, sI, N, P, p.port_len, p.z0, false);
+    lu_factor<float, Q, SB>(W, ld, N, N, N, sm, piv);
+    // x0 = (LU)^-1 V
+    for (int e = tid; e < N * P; e += kThreads) {
+      const int i = e / P, jr = e - i * P;
+      b[e] = float2{(i == N - P + jr) ? (float)p.port_len[jr] : 0.0f, 0.0f};
+    }
+    __syncthreads();
+    lu_solve_c64(W, ld, N, piv, b, P);
+    for (int e = tid; e < N * P; e += kThreads) x[e] = double2{(double)b[e].x, (double)b[e].y};
+    __syncthreads();
+    int iters = 0;
+    bool conv = false;
+    while (iters < p.ir_max) {
+      residual_fp64(Zf128, p.M, sI, N, P, p.port_len, p.z0, x, b);
+      lu_solve_c64(W, ld, N, piv, b, P);
+      if (tid == 0) s_conv = 1;
+      __syncthreads();
+      for (int e = tid; e < N * P; e += kThreads) {
+        const double2 d = double2{(double)b[e].x, (double)b[e].y};
+        double2 xv = x[e];
+        xv.x += d.x;
+        xv.y += d.y;
+        x[e] = xv;
+        if (e >= (N - P) * P) {  // port rows decide convergence
+          const double dm = sqrt(d.x * d.x + d.y * d.y), xm = sqrt(xv.x * xv.x + xv.y * xv.y);
+          if (!(dm <= p.ir_tol * xm)) s_conv = 0;
+        }
+      }
+      __syncthreads();
+      ++iters;
+      conv = s_conv != 0;
+      __syncthreads();
+      if (conv) break;
+    }
+    if (tid == 0) {
+      atomicAdd(p.ir_iters, iters);
+      int st = PXD_STATUS_OK;
+      if (!conv) {
+        st = PXD_STATUS_FALLBACK;
+        const int slotn = atomicAdd(p.fb_count, 1);
+        p.fb_list[slotn] = c * p.F + f;
+      } else {
+        bool finite = true;
+        for (int i = 0; i < P; ++i)
+          for (int j = 0; j < P; ++j) {
+            const double2 xv = x[(size_t)(N - P + i) * P + j];
+            const double2 sv = double2{(i == j ? 1.0 : 0.0) - 2.0 * p.z0 * p.port_len[i] * xv.x,
+                                       -2.0 * p.z0 * p.port_len[i] * xv.y};
+            finite = finite && isfinite(sv.x) && isfinite(sv.y);
+            Sout[i * P + j] = sv;
+          }
+        if (!finite) st = PXD_STATUS_NONFINITE;
+        else if (sm.bad) st = PXD_STATUS_SINGULAR;
+      }
+      p.status[(size_t)c * p.F + f] = st;
+    }
+    __syncthreads();
+  }
+}
+
+size_t eval_mixed_lds(int nmax, int P) { return ((size_t)nmax * 4 + 15) / 16 * 16 + (size_t)nmax * P * 8; }
 
 // ------------------------------------------------------------------ FoM and argmin
 
@@ -651,7 +963,24 @@ hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid) {
   return hipGetLastError();
 }
 
-hipError_t launch_eval_mixed(hipStream_t, const EvalParams&, int) { return hipErrorNotSupported; }
+template <int Q, int SB>
+static hipError_t launch_mixed_variant(hipStream_t s, const EvalParams& p, int grid, size_t lds) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval_mixed<Q, SB>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_eval_mixed<Q, SB>), dim3(grid), dim3(kThreads), lds, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_mixed(hipStream_t s, const EvalParams& p, int grid) {
+  const int Q = rows_per_thread(p.nmax);
+  const size_t lds = eval_mixed_lds(p.nmax, p.P);
+  if (Q <= 1) return launch_mixed_variant<1, 16>(s, p, grid, lds);
+  if (Q <= 2) return launch_mixed_variant<2, 8>(s, p, grid, lds);
+  if (Q <= 4) return launch_mixed_variant<4, 4>(s, p, grid, lds);
+  if (Q <= 8) return launch_mixed_variant<8, 2>(s, p, grid, lds);
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_fom(hipStream_t s, const double2* S, int C, int F, int P, const pxd_fom_term* terms,
                       const double* term_fac, int n_terms, const int8_t* band, const int* item_status, double* fom,

@@ -21,7 +21,9 @@ struct EvalParams {
   const double* port_len;
   double z0;
   int n_items;          // items to process in this launch
+  const int* n_items_dev; // if set, the item count is read from device memory instead
   const int* item_list; // explicit items (c * F + f), or null for the implicit frequency-major order
+  int fallback_mode;    // FP64 re-solve of items the mixed path could not refine: report FALLBACK
   int* counter;         // persistent work counter (zeroed before the launch)
   char* ws;             // workspace, one slot per workgroup
   size_t slot_bytes;
@@ -31,6 +33,7 @@ struct EvalParams {
   int* fb_list;         // mixed: items handed to the FP64 path
   int* fb_count;
   int* ir_iters;        // mixed: refinement iterations summed (one counter)
+  int ld;               // leading dimension of the slot matrix
   int ir_max;
   double ir_tol;
 };
@@ -71,6 +74,8 @@ hipError_t launch_order(hipStream_t s, const int* Nc, int C, int* order);
 hipError_t launch_fill_int(hipStream_t s, int* p, int n, int v);
 hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid);
 hipError_t launch_eval_mixed(hipStream_t s, const EvalParams& p, int grid);
+// dynamic LDS of the mixed evaluator for a given largest active size and port count
+size_t eval_mixed_lds(int nmax, int P);
 hipError_t launch_fom(hipStream_t s, const double2* S, int C, int F, int P, const pxd_fom_term* terms,
                       const double* term_fac, int n_terms, const int8_t* band, const int* item_status, double* fom,
                       int* cand_status);

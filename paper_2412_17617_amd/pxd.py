@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpxd.so")
+LIB_PATH = os.environ.get("PXD_LIB_PATH") or os.path.join(_HERE, "libpxd.so")
 
 OK, EINVAL, ENOMEM, ENOTLOADED, EDEVICE, ESHAPE = 0, -1, -2, -3, -4, -5
 PREC_FP64, PREC_MIXED32 = 0, 1
@@ -161,7 +161,7 @@ class Problem:
 class Evaluator:
     """GPU evaluator context (one per device and host thread)."""
 
-    def __init__(self, device=0, precision=PREC_FP64, ir_max_iter=10, ir_tol=1e-10, wg_per_cu=0, panel=0):
+    def __init__(self, device=0, precision=PREC_FP64, ir_max_iter=10, ir_tol=1e-7, wg_per_cu=0, panel=0):
         o = Options(device, precision, ir_max_iter, ir_tol, wg_per_cu, panel)
         h_ = _VP()
         _check(lib().pxd_create(C.byref(o), C.byref(h_)))
