@@ -38,6 +38,30 @@ def lu_flops(N, P):
     return (8.0 / 3.0) * N ** 3 + 8.0 * P * N ** 2
 
 
+KERNEL_OF = {"fp64": "k_eval_plain", "mixed32": "k_eval_mixed"}
+
+
+def measured_traffic(workload, mode, items):
+    """HBM bytes per launch of the evaluator kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    none for this workload or the kernel sources changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_eval_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    k = rec["kernels"].get(KERNEL_OF[mode])
+    if h.hexdigest() != rec["source_sha256"] or k is None or rec["items_per_launch"] != items:
+        return None
+    return k["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(spec, gpu_S, sample_c, seconds):
     """Time the oracle (as it stands) on a bounded sample of the same
     workload: its own parent fill at one frequency (not timed), then Eq. 5
@@ -95,6 +119,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fill-threads", type=int, default=16)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device, a reference kernel of known traffic for "
+                         "byte counters (FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (the path shards by frequency "
@@ -105,6 +132,14 @@ def main():
 
     from paper_2412_17617_amd import pxd
     from synth import get_spec
+
+    if args.copy_calibration:
+        src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()
+        dst = src.clone()  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 1 GiB device-to-device copy done")
 
     spec = get_spec(args.workload)
     freqs = spec.freqs
@@ -211,14 +246,20 @@ def main():
             "unit": "TFLOP/s",
             "frac": r["achieved"] / r["peak"],
             "traffic": None,
-            "kernel": "k_eval_plain" if chosen == "fp64" else "k_eval_mixed",
+            "kernel": KERNEL_OF[chosen],
             "kernel_ms": r["kernel_ms"],
         },
     }
+    traffic = measured_traffic(spec.name, chosen, C * spec.n_freq)
+    if traffic is not None:
+        out["roofline"]["traffic"] = traffic
+        out["roofline"]["traffic_unit"] = "bytes/launch"
+        out["roofline"]["traffic_TBps"] = traffic / (r["kernel_ms"] / 1e3) / 1e12
     if "fp64" in results and chosen != "fp64":
         f64 = results["fp64"]
         out["fp64_plain"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"], "kernel_ms": f64["kernel_ms"],
-                             "roofline_frac": f64["achieved"] / f64["peak"], "achieved_tflops": f64["achieved"]}
+                             "roofline_frac": f64["achieved"] / f64["peak"], "achieved_tflops": f64["achieved"],
+                             "traffic": measured_traffic(spec.name, "fp64", C * spec.n_freq)}
         out["speedup_vs_fp64_plain"] = r["value"] / f64["value"]
         out["config"]["max_dS_vs_fp64_plain"] = float(np.abs(r["S_sample"] - f64["S_sample"]).max())
         out["config"]["argmin_equal_fp64_plain"] = bool(r["am"] == f64["am"])

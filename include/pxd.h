@@ -107,8 +107,9 @@ typedef struct pxd_options {
   int32_t device;          /* HIP device ordinal */
   int32_t precision;       /* PXD_PREC_* */
   int32_t ir_max_iter;     /* refinement iterations before FP64 fallback (default 10) */
-  double ir_tol;           /* stop when every port-current correction is below ir_tol of it (default 1e-7);
-                              the correction is applied, so the result is ~ir_tol x contraction accurate */
+  double ir_tol;           /* stop when the last correction changed no S entry by more than ir_tol
+                              (absolute, |dS_ij| = 2 Z0 l_i |d_i^(j)|; default 1e-7); the correction is
+                              applied, so the result is about ir_tol x the contraction factor accurate */
   int32_t wg_per_cu;       /* persistent workgroups per compute unit (0 = 2) */
   int32_t panel;           /* LU panel width, 16 or 32 (0 = 32) */
 } pxd_options;

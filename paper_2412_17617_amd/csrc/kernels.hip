@@ -774,9 +774,9 @@ __device__ __forceinline__ void residual_fp64(const double2* __restrict__ Zf, in
 }
 
 // Mixed precision item: complex64 LU of Z_A, initial complex64 solve, then
-// refinement with FP64 residuals until every port current's correction is
-// below ir_tol relative to it.  Items that do not converge are queued for the
-// FP64 path.
+// refinement with FP64 residuals until the correction of every port current,
+// expressed as the change it makes to S_ij = delta_ij - 2 Z0 l_i x_ij, is at
+// most ir_tol.  Items that do not converge are queued for the FP64 path.
 template <int Q, int SB>
 __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
   using T = float2;
@@ -835,9 +835,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
         xv.x += d.x;
         xv.y += d.y;
         x[e] = xv;
-        if (e >= (N - P) * P) {  // port rows decide convergence
-          const double dm = sqrt(d.x * d.x + d.y * d.y), xm = sqrt(xv.x * xv.x + xv.y * xv.y);
-          if (!(dm <= p.ir_tol * xm)) s_conv = 0;
+        if (e >= (N - P) * P) {  // port rows decide convergence: the change of S_ij (Eq. 6) this step made
+          const int pi = e / P - (N - P);
+          const double ds = 2.0 * p.z0 * p.port_len[pi] * sqrt(d.x * d.x + d.y * d.y);
+          if (!(ds <= p.ir_tol)) s_conv = 0;
         }
       }
       __syncthreads();
