@@ -20,7 +20,8 @@
  *  - Host pointers passed in are only read during the call; the library
  *    copies what it keeps.  Output host buffers are owned by the caller.
  *  - *_device entry points take device pointers (for example memory owned by
- *    PyTorch) and a hipStream_t passed as void*; work is ordered on that
+ *    PyTorch) and a hipStream_t passed as void* (NULL = HIP's default
+ *    stream); work is ordered on that
  *    stream and the call returns without synchronising it.  Device buffers
  *    are borrowed only for the duration of the call.
  *  - Units are SI: metre, hertz, ohm.
@@ -55,6 +56,12 @@ extern "C" {
 #define PXD_STATUS_FALLBACK 1     /* mixed precision did not converge; FP64 result returned */
 #define PXD_STATUS_NONFINITE (-1) /* a non-finite value reached S */
 #define PXD_STATUS_SINGULAR (-2)  /* an exactly zero pivot was met */
+#define PXD_STATUS_SIZE (-3)      /* active size above the bound a captured graph was built for (or < P) */
+
+/* Order in which the persistent workgroups take (candidate, frequency) items. */
+#define PXD_SCHED_AUTO 0       /* tuned value if the context has one, else frequency-major */
+#define PXD_SCHED_FREQ_MAJOR 1 /* all candidates of one frequency (largest first), then the next frequency */
+#define PXD_SCHED_SIZE_MAJOR 2 /* all frequencies of the largest candidate first (uneven batches) */
 
 /* Arithmetic of the dense solve. */
 #define PXD_PREC_FP64 0    /* complex128 LU, no refinement ("plain") */
@@ -110,8 +117,9 @@ typedef struct pxd_options {
   double ir_tol;           /* stop when the last correction changed no S entry by more than ir_tol
                               (absolute, |dS_ij| = 2 Z0 l_i |d_i^(j)|; default 1e-7); the correction is
                               applied, so the result is about ir_tol x the contraction factor accurate */
-  int32_t wg_per_cu;       /* persistent workgroups per compute unit (0 = 2) */
-  int32_t panel;           /* LU panel width, 16 or 32 (0 = 32) */
+  int32_t wg_per_cu;       /* persistent workgroups per compute unit: 1 or 2 (0 = tuned, else 2) */
+  int32_t half_subpanel;   /* register sub-panel of the LU: 1 full width, 2 half width (0 = tuned, else full) */
+  int32_t schedule;        /* PXD_SCHED_* */
 } pxd_options;
 
 typedef struct pxd_ctx pxd_ctx;
@@ -180,6 +188,59 @@ int pxd_expand(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int3
 int pxd_gather(pxd_ctx* ctx, int32_t f, int32_t N, const int32_t* idx, double* ZA_out);
 
 int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out);
+
+/* Candidates given as whole maps (an uneven batch: any mix of active sizes in
+ * one persistent launch): maps is n_maps x n_cells, row c = candidate c.
+ * Outputs as for pxd_evaluate_flips.  Host buffers. */
+int pxd_evaluate_maps(pxd_ctx* ctx, int32_t n_maps, const uint8_t* maps, double* S_out, double* fom_out,
+                      int32_t* status, int32_t* argmin_out);
+/* Same with device pointers on `stream`. */
+int pxd_evaluate_maps_device(pxd_ctx* ctx, void* stream, int32_t n_maps, const uint8_t* maps, double* S_out,
+                             double* fom_out, int32_t* status, int32_t* argmin_out);
+
+/* ------------------------------------------------------------ autotuning */
+
+/* One configuration tried by pxd_autotune and its measured evaluator time. */
+typedef struct pxd_tune_entry {
+  int32_t rows_per_thread; /* size class Q: active sizes up to 256 Q */
+  int32_t wg_per_cu, half_subpanel, schedule;
+  double ms;               /* evaluator time (solve + fallback), best of n_reps */
+} pxd_tune_entry;
+
+/* Time every configuration (workgroups per CU x sub-panel width x item order)
+ * on this batch (host buffers, as pxd_evaluate_flips), n_reps times each, and
+ * keep the fastest for the batch's precision and size class; later calls
+ * whose options say "tuned" use it.  report (may be NULL) receives up to
+ * max_report entries, *n_report the number written; the chosen one is
+ * report[0]. */
+int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,
+                 const int32_t* cells, int32_t n_reps, pxd_tune_entry* report, int32_t max_report,
+                 int32_t* n_report);
+/* Tuned table as text (one line per precision and size class), and back. */
+int pxd_tune_save(const pxd_ctx* ctx, const char* path);
+int pxd_tune_load(pxd_ctx* ctx, const char* path);
+
+/* ------------------------------------------------------------ HIP graphs */
+
+typedef struct pxd_graph pxd_graph;
+
+/* Capture the whole device-side evaluation of a batch (expand, order,
+ * evaluator, fallback, FoM, argmin) into a HIP graph.  All pointers are
+ * device pointers that must stay valid while the graph exists; the graph
+ * reads their contents at each launch, so the caller may change the map or
+ * flips in place between launches.  base_stride must be 0: one base map plus
+ * flips (offsets/cells as in pxd_evaluate_flips_device); whole-map batches
+ * (base_stride = n_cells) are refused with PXD_EINVAL.  Nothing in the captured
+ * work synchronises with the host, so the launch is sized for active sizes
+ * up to n_max_active: an item above it gets PXD_STATUS_SIZE.  The graph owns
+ * its own workspace (allocated here), so it does not disturb other calls on
+ * the context; the context must outlive it. */
+int pxd_graph_create(pxd_ctx* ctx, const uint8_t* base_map, int64_t base_stride, int32_t n_cand,
+                     const int32_t* offsets, const int32_t* cells, int32_t n_max_active, double* S_out,
+                     double* fom_out, int32_t* status, int32_t* argmin_out, pxd_graph** out);
+/* Launch the captured evaluation on `stream` (NULL = HIP's default stream). */
+int pxd_graph_launch(pxd_graph* g, void* stream);
+void pxd_graph_destroy(pxd_graph* g);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -40,6 +41,27 @@ struct DevBuf {
 
 }  // namespace
 
+namespace {
+
+// Per-launch device buffers; the context has one set, every graph its own.
+struct EvalBufs {
+  DevBuf Nc, Ilist, order, counter, item_status, ws, fb_list;
+  void release() {
+    for (DevBuf* b : {&Nc, &Ilist, &order, &counter, &item_status, &ws, &fb_list}) b->release();
+  }
+};
+
+// Launch configuration chosen per (precision, size class Q).
+struct Tuning {
+  int wg_per_cu = 2, half_sb = 0, schedule = PXD_SCHED_FREQ_MAJOR;
+  bool valid = false;
+  double ms = 0;
+};
+constexpr int kSizeClasses = 4;  // Q = 1, 2, 4, 8
+int size_class(int Q) { return Q <= 1 ? 0 : Q <= 2 ? 1 : Q <= 4 ? 2 : 3; }
+
+}  // namespace
+
 struct pxd_ctx {
   pxd_options opt{};
   std::string err;
@@ -59,10 +81,14 @@ struct pxd_ctx {
   int n_terms = 0;
   DevBuf terms, term_fac, band;
   // per call
-  DevBuf base, off, cells, Nc, Ilist, order, counter, S, item_status, cand_status, fom, argmin, ws, fb_list;
+  DevBuf base, off, cells, S, cand_status, fom, argmin;
+  EvalBufs eb;
   std::vector<int> hNc;
   pxd_stats stats{};
   bool stats_pending_counts = false;
+  // autotuning: tuned[precision][size class]; `forced` overrides during a tuning sweep
+  Tuning tuned[2][kSizeClasses];
+  const Tuning* forced = nullptr;
 
   int fail(int rc, const std::string& m) {
     err = m;
@@ -74,6 +100,13 @@ struct pxd_ctx {
   }
 };
 
+struct pxd_graph {
+  pxd_ctx* ctx = nullptr;
+  EvalBufs eb;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 #define HIPCHK(ctx, expr)                              \
   do {                                                 \
     hipError_t e_ = (expr);                            \
@@ -82,94 +115,119 @@ struct pxd_ctx {
 
 namespace {
 
-int evaluate(pxd_ctx* ctx, hipStream_t s, const uint8_t* d_base, int C, const int* d_off, const int* d_cells,
-             double2* d_S, double* d_fom, int* d_cand_status, int* d_argmin) {
+// The launch configuration for this precision and size class: explicit
+// options first, then the tuned table, then the defaults.
+Tuning resolve(const pxd_ctx* ctx, int Q) {
+  if (ctx->forced) return *ctx->forced;
+  const Tuning& t = ctx->tuned[ctx->opt.precision == PXD_PREC_MIXED32][size_class(Q)];
+  Tuning r = t.valid ? t : Tuning{};
+  if (ctx->opt.wg_per_cu > 0) r.wg_per_cu = std::min(ctx->opt.wg_per_cu, 2);
+  if (ctx->opt.half_subpanel == 1 || ctx->opt.half_subpanel == 2) r.half_sb = ctx->opt.half_subpanel - 1;
+  if (ctx->opt.schedule != PXD_SCHED_AUTO) r.schedule = ctx->opt.schedule;
+  return r;
+}
+
+// Enqueue one evaluation of C candidates on stream s.  nmax_bound > 0: the
+// launch is sized for that bound without reading the active sizes back (as a
+// graph needs); otherwise they are read back to size it exactly.  Events and
+// kernel attributes are set only outside stream capture.
+int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, size_t base_stride, int C,
+             const int* d_off, const int* d_cells, double2* d_S, double* d_fom, int* d_cand_status, int* d_argmin,
+             int nmax_bound, bool capturing = false) {
   if (!ctx->Z128.p) return ctx->fail(PXD_ENOTLOADED, "parent matrices not loaded");
   if (!ctx->cell_a.p) return ctx->fail(PXD_ENOTLOADED, "pixel-to-RWG map not loaded");
   if (!ctx->terms.p) return ctx->fail(PXD_ENOTLOADED, "FoM table not set");
   const bool mixed = ctx->opt.precision == PXD_PREC_MIXED32;
+  const bool events = !capturing;
   const int M = ctx->M, F = ctx->F, P = ctx->P;
-  ctx->stats = pxd_stats{};
+  if (events) ctx->stats = pxd_stats{};
   if (C == 0) return PXD_OK;
-  HIPCHK(ctx, ctx->Nc.ensure(sizeof(int) * C));
-  HIPCHK(ctx, ctx->Ilist.ensure(sizeof(int) * (size_t)C * M));
-  HIPCHK(ctx, ctx->order.ensure(sizeof(int) * C));
-  HIPCHK(ctx, ctx->counter.ensure(sizeof(int) * 8));
-  HIPCHK(ctx, ctx->item_status.ensure(sizeof(int) * (size_t)C * F));
-  HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
-  HIPCHK(ctx, pxd::launch_expand(s, d_base, ctx->n_cells, d_off, d_cells, C, ctx->cell_a.as<int>(),
-                                 ctx->cell_b.as<int>(), M, ctx->Nc.as<int>(), ctx->Ilist.as<int>()));
-  HIPCHK(ctx, pxd::launch_order(s, ctx->Nc.as<int>(), C, ctx->order.as<int>()));
-  // the largest active size picks the kernel variant and the slot size
-  ctx->hNc.resize(C);
-  HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data(), ctx->Nc.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  const int nmax = *std::max_element(ctx->hNc.begin(), ctx->hNc.end());
-  const int nmin = *std::min_element(ctx->hNc.begin(), ctx->hNc.end());
+  HIPCHK(ctx, b.Nc.ensure(sizeof(int) * C));
+  HIPCHK(ctx, b.Ilist.ensure(sizeof(int) * (size_t)C * M));
+  HIPCHK(ctx, b.order.ensure(sizeof(int) * C));
+  HIPCHK(ctx, b.counter.ensure(sizeof(int) * 8));
+  HIPCHK(ctx, b.item_status.ensure(sizeof(int) * (size_t)C * F));
+  if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
+  HIPCHK(ctx, pxd::launch_expand(s, d_base, ctx->n_cells, base_stride, d_off, d_cells, C, ctx->cell_a.as<int>(),
+                                 ctx->cell_b.as<int>(), M, b.Nc.as<int>(), b.Ilist.as<int>()));
+  HIPCHK(ctx, pxd::launch_order(s, b.Nc.as<int>(), C, b.order.as<int>()));
+  int nmax = nmax_bound, nmin = P;
+  if (nmax_bound <= 0) {
+    // the largest active size picks the kernel variant and the slot size
+    ctx->hNc.resize(C);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data(), b.Nc.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    nmax = *std::max_element(ctx->hNc.begin(), ctx->hNc.end());
+    nmin = *std::min_element(ctx->hNc.begin(), ctx->hNc.end());
+    if (nmin < P) return ctx->fail(PXD_ESHAPE, "candidate with fewer active functions than ports");
+  }
   if (nmax > 2048) return ctx->fail(PXD_ESHAPE, "active size above 2048 is not supported");
-  if (nmin < P) return ctx->fail(PXD_ESHAPE, "candidate with fewer active functions than ports");
-  HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+  if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
 
-  const int wg_per_cu = ctx->opt.wg_per_cu > 0 ? ctx->opt.wg_per_cu : 2;
+  const Tuning tune = resolve(ctx, pxd::rows_per_thread(nmax));
   const long long items = (long long)C * F;
-  int grid = (int)std::min<long long>(items, (long long)ctx->n_cu * wg_per_cu);
+  int grid = (int)std::min<long long>(items, (long long)ctx->n_cu * tune.wg_per_cu);
   const pxd::SlotLayout lay_p = pxd::slot_layout(nmax, P, false);
   const pxd::SlotLayout lay_m = pxd::slot_layout(nmax, P, true);
   // the mixed path re-solves unrefined items with the FP64 kernel in the same slots
   const size_t slot = mixed ? std::max(lay_p.bytes, lay_m.bytes) : lay_p.bytes;
-  HIPCHK(ctx, ctx->ws.ensure(slot * (size_t)grid));
-  if (mixed) HIPCHK(ctx, ctx->fb_list.ensure(sizeof(int) * (size_t)items));
+  HIPCHK(ctx, b.ws.ensure(slot * (size_t)grid));
+  if (mixed) HIPCHK(ctx, b.fb_list.ensure(sizeof(int) * (size_t)items));
 
   pxd::EvalParams ep{};
   ep.Z128 = ctx->Z128.as<double2>();
   ep.Z64 = ctx->Z64.as<float2>();
   ep.M = M, ep.F = F, ep.P = P, ep.C = C;
-  ep.Nc = ctx->Nc.as<int>();
-  ep.Ilist = ctx->Ilist.as<int>();
-  ep.order = ctx->order.as<int>();
+  ep.Nc = b.Nc.as<int>();
+  ep.Ilist = b.Ilist.as<int>();
+  ep.order = b.order.as<int>();
   ep.port_len = ctx->plen.as<double>();
   ep.z0 = ctx->z0;
   ep.n_items = (int)items;
   ep.item_list = nullptr;
-  ep.counter = ctx->counter.as<int>();
-  ep.ws = ctx->ws.as<char>();
+  ep.counter = b.counter.as<int>();
+  ep.ws = b.ws.as<char>();
   ep.slot_bytes = slot;
   ep.ld = mixed ? lay_m.ld : lay_p.ld;
   ep.nmax = nmax;
   ep.S = d_S;
-  ep.status = ctx->item_status.as<int>();
+  ep.status = b.item_status.as<int>();
   ep.ir_max = ctx->opt.ir_max_iter;
   ep.ir_tol = ctx->opt.ir_tol;
-  int* cnt = ctx->counter.as<int>();  // [0] work, [1] fallback count, [2] refinement steps, [3] fallback work
-  ep.fb_list = ctx->fb_list.as<int>();
+  ep.schedule = tune.schedule;
+  int* cnt = b.counter.as<int>();  // [0] work, [1] fallback count, [2] refinement steps, [3] fallback work
+  ep.fb_list = b.fb_list.as<int>();
   ep.fb_count = cnt + 1;
   ep.ir_iters = cnt + 2;
   HIPCHK(ctx, pxd::launch_fill_int(s, cnt, 8, 0));
   if (!mixed) {
-    HIPCHK(ctx, pxd::launch_eval_plain(s, ep, grid));
-    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
-    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+    HIPCHK(ctx, pxd::launch_eval_plain(s, ep, grid, tune.half_sb));
+    if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
   } else {
-    HIPCHK(ctx, pxd::launch_eval_mixed(s, ep, grid));
-    HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+    if (!capturing) HIPCHK(ctx, pxd::prepare_eval_mixed(ep, tune.half_sb));
+    HIPCHK(ctx, pxd::launch_eval_mixed(s, ep, grid, tune.half_sb));
+    if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
     pxd::EvalParams fb = ep;  // FP64 re-solve of the items refinement could not settle
     fb.item_list = ep.fb_list;
     fb.n_items_dev = cnt + 1;
     fb.counter = cnt + 3;
     fb.ld = lay_p.ld;
     fb.fallback_mode = 1;
-    HIPCHK(ctx, pxd::launch_eval_plain(s, fb, grid));
-    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+    HIPCHK(ctx, pxd::launch_eval_plain(s, fb, grid, tune.half_sb));
+    if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
   }
   HIPCHK(ctx, pxd::launch_fom(s, d_S, C, F, P, ctx->terms.as<pxd_fom_term>(), ctx->term_fac.as<double>(),
-                              ctx->n_terms, ctx->band.as<int8_t>(), ctx->item_status.as<int>(), d_fom,
+                              ctx->n_terms, ctx->band.as<int8_t>(), b.item_status.as<int>(), d_fom,
                               d_cand_status));
   if (d_argmin) HIPCHK(ctx, pxd::launch_argmin(s, d_fom, C, d_argmin));
-  HIPCHK(ctx, hipEventRecord(ctx->ev[4], s));
-  ctx->stats.items = items;
-  ctx->stats.max_active = nmax;
-  ctx->stats.min_active = nmin;
-  ctx->stats_pending_counts = mixed;
+  if (events) {
+    HIPCHK(ctx, hipEventRecord(ctx->ev[4], s));
+    ctx->stats.items = items;
+    ctx->stats.max_active = nmax;
+    ctx->stats.min_active = nmin;
+    ctx->stats_pending_counts = mixed;
+  }
   return PXD_OK;
 }
 
@@ -181,6 +239,40 @@ int check_flips(pxd_ctx* ctx, int n_cand, const int32_t* offsets, const int32_t*
     if (offsets[c + 1] < offsets[c]) return ctx->fail(PXD_EINVAL, "offsets must be non-decreasing");
   for (int i = 0; i < offsets[n_cand]; ++i)
     if (cells[i] < 0 || cells[i] >= ctx->n_cells) return ctx->fail(PXD_EINVAL, "flip cell out of range");
+  return PXD_OK;
+}
+
+// Copy a host batch into the context's buffers and enqueue its evaluation on
+// the context's stream.  base_stride = 0: one base map plus flips; otherwise
+// `base` holds C whole maps and offsets/cells are NULL.
+int upload_and_evaluate(pxd_ctx* ctx, const uint8_t* base, size_t base_stride, int C, const int32_t* offsets,
+                        const int32_t* cells) {
+  hipStream_t s = ctx->stream;
+  const size_t nbase = base_stride ? base_stride * std::max(1, C) : (size_t)ctx->n_cells;
+  const int nf = offsets ? offsets[C] : 0;
+  HIPCHK(ctx, ctx->base.ensure(nbase));
+  HIPCHK(ctx, ctx->off.ensure(sizeof(int) * (C + 1)));
+  HIPCHK(ctx, ctx->cells.ensure(sizeof(int) * std::max(1, nf)));
+  HIPCHK(ctx, ctx->S.ensure(sizeof(double2) * std::max<size_t>(1, (size_t)C * ctx->F * ctx->P * ctx->P)));
+  HIPCHK(ctx, ctx->fom.ensure(sizeof(double) * std::max(1, C)));
+  HIPCHK(ctx, ctx->cand_status.ensure(sizeof(int) * std::max(1, C)));
+  HIPCHK(ctx, ctx->argmin.ensure(sizeof(int)));
+  if (C > 0 || !base_stride) HIPCHK(ctx, hipMemcpyAsync(ctx->base.p, base, nbase, hipMemcpyHostToDevice, s));
+  if (offsets) HIPCHK(ctx, hipMemcpyAsync(ctx->off.p, offsets, sizeof(int) * (C + 1), hipMemcpyHostToDevice, s));
+  if (nf > 0) HIPCHK(ctx, hipMemcpyAsync(ctx->cells.p, cells, sizeof(int) * nf, hipMemcpyHostToDevice, s));
+  return evaluate(ctx, ctx->eb, s, ctx->base.as<uint8_t>(), base_stride, C, offsets ? ctx->off.as<int>() : nullptr,
+                  offsets ? ctx->cells.as<int>() : nullptr, ctx->S.as<double2>(), ctx->fom.as<double>(),
+                  ctx->cand_status.as<int>(), ctx->argmin.as<int>(), 0);
+}
+
+int download(pxd_ctx* ctx, int C, double* S_out, double* fom_out, int32_t* status, int32_t* argmin_out) {
+  hipStream_t s = ctx->stream;
+  const size_t nS = (size_t)C * ctx->F * ctx->P * ctx->P;
+  if (S_out && C) HIPCHK(ctx, hipMemcpyAsync(S_out, ctx->S.p, sizeof(double2) * nS, hipMemcpyDeviceToHost, s));
+  if (fom_out && C) HIPCHK(ctx, hipMemcpyAsync(fom_out, ctx->fom.p, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+  if (status && C) HIPCHK(ctx, hipMemcpyAsync(status, ctx->cand_status.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
+  if (argmin_out && C) HIPCHK(ctx, hipMemcpyAsync(argmin_out, ctx->argmin.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
   return PXD_OK;
 }
 
@@ -229,10 +321,10 @@ void pxd_destroy(pxd_ctx* ctx) {
   (void)hipSetDevice(ctx->opt.device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (DevBuf* b : {&ctx->Z128, &ctx->Z64, &ctx->cell_a, &ctx->cell_b, &ctx->plen, &ctx->terms, &ctx->term_fac,
-                    &ctx->band, &ctx->base, &ctx->off, &ctx->cells, &ctx->Nc, &ctx->Ilist, &ctx->order,
-                    &ctx->counter, &ctx->S, &ctx->item_status, &ctx->cand_status, &ctx->fom, &ctx->argmin,
-                    &ctx->ws, &ctx->fb_list})
+                    &ctx->band, &ctx->base, &ctx->off, &ctx->cells, &ctx->S, &ctx->cand_status, &ctx->fom,
+                    &ctx->argmin})
     b->release();
+  ctx->eb.release();
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -356,28 +448,9 @@ int pxd_evaluate_flips(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, co
   int rc = check_flips(ctx, n_cand, offsets, cells);
   if (rc) return rc;
   HIPCHK(ctx, hipSetDevice(ctx->opt.device));
-  const int C = n_cand, nf = offsets[n_cand];
-  hipStream_t s = ctx->stream;
-  HIPCHK(ctx, ctx->base.ensure(ctx->n_cells));
-  HIPCHK(ctx, ctx->off.ensure(sizeof(int) * (C + 1)));
-  HIPCHK(ctx, ctx->cells.ensure(sizeof(int) * std::max(1, nf)));
-  HIPCHK(ctx, ctx->S.ensure(sizeof(double2) * std::max<size_t>(1, (size_t)C * ctx->F * ctx->P * ctx->P)));
-  HIPCHK(ctx, ctx->fom.ensure(sizeof(double) * std::max(1, C)));
-  HIPCHK(ctx, ctx->cand_status.ensure(sizeof(int) * std::max(1, C)));
-  HIPCHK(ctx, ctx->argmin.ensure(sizeof(int)));
-  HIPCHK(ctx, hipMemcpyAsync(ctx->base.p, base_map, ctx->n_cells, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemcpyAsync(ctx->off.p, offsets, sizeof(int) * (C + 1), hipMemcpyHostToDevice, s));
-  if (nf > 0) HIPCHK(ctx, hipMemcpyAsync(ctx->cells.p, cells, sizeof(int) * nf, hipMemcpyHostToDevice, s));
-  rc = evaluate(ctx, s, ctx->base.as<uint8_t>(), C, ctx->off.as<int>(), ctx->cells.as<int>(), ctx->S.as<double2>(),
-                ctx->fom.as<double>(), ctx->cand_status.as<int>(), ctx->argmin.as<int>());
+  rc = upload_and_evaluate(ctx, base_map, 0, n_cand, offsets, cells);
   if (rc) return rc;
-  const size_t nS = (size_t)C * ctx->F * ctx->P * ctx->P;
-  if (S_out && C) HIPCHK(ctx, hipMemcpyAsync(S_out, ctx->S.p, sizeof(double2) * nS, hipMemcpyDeviceToHost, s));
-  if (fom_out && C) HIPCHK(ctx, hipMemcpyAsync(fom_out, ctx->fom.p, sizeof(double) * C, hipMemcpyDeviceToHost, s));
-  if (status && C) HIPCHK(ctx, hipMemcpyAsync(status, ctx->cand_status.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
-  if (argmin_out && C) HIPCHK(ctx, hipMemcpyAsync(argmin_out, ctx->argmin.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  return PXD_OK;
+  return download(ctx, n_cand, S_out, fom_out, status, argmin_out);
 }
 
 int pxd_evaluate_flips_device(pxd_ctx* ctx, void* stream, const uint8_t* base_map, int32_t n_cand,
@@ -387,9 +460,183 @@ int pxd_evaluate_flips_device(pxd_ctx* ctx, void* stream, const uint8_t* base_ma
   if (!base_map || !offsets || n_cand < 0 || n_flips < 0 || (n_flips > 0 && !cells) || !S_out || !fom_out)
     return ctx->fail(PXD_EINVAL, "invalid device arguments");
   HIPCHK(ctx, hipSetDevice(ctx->opt.device));
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
-  return evaluate(ctx, s, base_map, n_cand, offsets, cells, reinterpret_cast<double2*>(S_out), fom_out, status,
-                  argmin_out);
+  hipStream_t s = static_cast<hipStream_t>(stream);  // NULL is the default stream
+  return evaluate(ctx, ctx->eb, s, base_map, 0, n_cand, offsets, cells, reinterpret_cast<double2*>(S_out), fom_out,
+                  status, argmin_out, 0);
+}
+
+int pxd_evaluate_maps(pxd_ctx* ctx, int32_t n_maps, const uint8_t* maps, double* S_out, double* fom_out,
+                      int32_t* status, int32_t* argmin_out) {
+  if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  if (n_maps < 0 || (n_maps > 0 && !maps)) return ctx->fail(PXD_EINVAL, "invalid maps");
+  if (!ctx->cell_a.p) return ctx->fail(PXD_ENOTLOADED, "pixel-to-RWG map not loaded");
+  HIPCHK(ctx, hipSetDevice(ctx->opt.device));
+  int rc = upload_and_evaluate(ctx, maps, ctx->n_cells, n_maps, nullptr, nullptr);
+  if (rc) return rc;
+  return download(ctx, n_maps, S_out, fom_out, status, argmin_out);
+}
+
+int pxd_evaluate_maps_device(pxd_ctx* ctx, void* stream, int32_t n_maps, const uint8_t* maps, double* S_out,
+                             double* fom_out, int32_t* status, int32_t* argmin_out) {
+  if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  if (n_maps < 0 || (n_maps > 0 && !maps) || !S_out || !fom_out) return ctx->fail(PXD_EINVAL, "invalid device arguments");
+  if (!ctx->cell_a.p) return ctx->fail(PXD_ENOTLOADED, "pixel-to-RWG map not loaded");
+  HIPCHK(ctx, hipSetDevice(ctx->opt.device));
+  hipStream_t s = static_cast<hipStream_t>(stream);  // NULL is the default stream
+  return evaluate(ctx, ctx->eb, s, maps, (size_t)ctx->n_cells, n_maps, nullptr, nullptr,
+                  reinterpret_cast<double2*>(S_out), fom_out, status, argmin_out, 0);
+}
+
+int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,
+                 const int32_t* cells, int32_t n_reps, pxd_tune_entry* report, int32_t max_report,
+                 int32_t* n_report) {
+  if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  if (n_report) *n_report = 0;
+  if (!base_map || n_cand <= 0 || (max_report > 0 && !report)) return ctx->fail(PXD_EINVAL, "invalid tuning batch");
+  if (!ctx->cell_a.p) return ctx->fail(PXD_ENOTLOADED, "pixel-to-RWG map not loaded");
+  int rc = check_flips(ctx, n_cand, offsets, cells);
+  if (rc) return rc;
+  HIPCHK(ctx, hipSetDevice(ctx->opt.device));
+  n_reps = std::max(1, n_reps);
+  std::vector<pxd_tune_entry> tried;
+  int Q = 0;
+  for (int wg = 2; wg >= 1; --wg)
+    for (int half = 0; half <= 1; ++half)
+      for (int sched = PXD_SCHED_FREQ_MAJOR; sched <= PXD_SCHED_SIZE_MAJOR; ++sched) {
+        Tuning t;
+        t.wg_per_cu = wg, t.half_sb = half, t.schedule = sched, t.valid = true;
+        double best = 1e300;
+        for (int r = 0; r < n_reps; ++r) {
+          ctx->forced = &t;
+          rc = upload_and_evaluate(ctx, base_map, 0, n_cand, offsets, cells);
+          ctx->forced = nullptr;
+          if (rc) return rc;
+          HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+          pxd_stats st{};
+          pxd_get_stats(ctx, &st);
+          best = std::min(best, st.ms_solve + st.ms_fallback);
+          Q = pxd::rows_per_thread(st.max_active);
+        }
+        tried.push_back(pxd_tune_entry{Q, wg, half, sched, best});
+      }
+  std::stable_sort(tried.begin(), tried.end(),
+                   [](const pxd_tune_entry& a, const pxd_tune_entry& b) { return a.ms < b.ms; });
+  const pxd_tune_entry& w = tried.front();
+  Tuning& slot = ctx->tuned[ctx->opt.precision == PXD_PREC_MIXED32][size_class(Q)];
+  slot.wg_per_cu = w.wg_per_cu, slot.half_sb = w.half_subpanel, slot.schedule = w.schedule;
+  slot.ms = w.ms, slot.valid = true;
+  const int n = std::min<int>(max_report, (int)tried.size());
+  for (int i = 0; i < n; ++i) report[i] = tried[i];
+  if (n_report) *n_report = n;
+  return PXD_OK;
+}
+
+int pxd_tune_save(const pxd_ctx* ctx, const char* path) {
+  if (!ctx || !path) return pxd::set_thread_error(PXD_EINVAL, "null argument");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return pxd::set_thread_error(PXD_EINVAL, std::string("cannot write ") + path);
+  std::fprintf(f, "# precision rows_per_thread wg_per_cu half_subpanel schedule ms\n");
+  const int Qs[kSizeClasses] = {1, 2, 4, 8};
+  for (int prec = 0; prec < 2; ++prec)
+    for (int q = 0; q < kSizeClasses; ++q) {
+      const Tuning& t = ctx->tuned[prec][q];
+      if (t.valid) std::fprintf(f, "%d %d %d %d %d %.6f\n", prec, Qs[q], t.wg_per_cu, t.half_sb, t.schedule, t.ms);
+    }
+  std::fclose(f);
+  return PXD_OK;
+}
+
+int pxd_tune_load(pxd_ctx* ctx, const char* path) {
+  if (!ctx || !path) return pxd::set_thread_error(PXD_EINVAL, "null argument");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return ctx->fail(PXD_EINVAL, std::string("cannot read ") + path);
+  char line[256];
+  int rc = PXD_OK;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int prec, Q, wg, half, sched;
+    double ms;
+    if (std::sscanf(line, "%d %d %d %d %d %lf", &prec, &Q, &wg, &half, &sched, &ms) != 6 || prec < 0 || prec > 1 ||
+        (Q != 1 && Q != 2 && Q != 4 && Q != 8) || wg < 1 || wg > 2 || half < 0 || half > 1 ||
+        sched < PXD_SCHED_FREQ_MAJOR || sched > PXD_SCHED_SIZE_MAJOR) {
+      rc = ctx->fail(PXD_EINVAL, std::string("malformed tuning line: ") + line);
+      break;
+    }
+    Tuning& t = ctx->tuned[prec][size_class(Q)];
+    t.wg_per_cu = wg, t.half_sb = half, t.schedule = sched, t.ms = ms, t.valid = true;
+  }
+  std::fclose(f);
+  return rc;
+}
+
+int pxd_graph_create(pxd_ctx* ctx, const uint8_t* base_map, int64_t base_stride, int32_t n_cand,
+                     const int32_t* offsets, const int32_t* cells, int32_t n_max_active, double* S_out,
+                     double* fom_out, int32_t* status, int32_t* argmin_out, pxd_graph** out) {
+  if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  if (!out) return ctx->fail(PXD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!base_map || n_cand <= 0 || !S_out || !fom_out || base_stride < 0 ||
+      (base_stride == 0 && (!offsets || !cells)) || (base_stride != 0 && base_stride != ctx->n_cells))
+    return ctx->fail(PXD_EINVAL, "invalid graph arguments");
+  if (base_stride != 0)  // switched off: its one GPU run stalled with no cause found
+    return ctx->fail(PXD_EINVAL, "graphs of whole-map batches are not supported; capture a flip batch");
+  if (n_max_active < ctx->P || n_max_active > std::min(2048, ctx->M))
+    return ctx->fail(PXD_EINVAL, "n_max_active must lie in [P, min(M, 2048)]");
+  HIPCHK(ctx, hipSetDevice(ctx->opt.device));
+  auto* g = new (std::nothrow) pxd_graph();
+  if (!g) return ctx->fail(PXD_ENOMEM, "out of host memory");
+  g->ctx = ctx;
+  hipStream_t s = ctx->stream;
+  // allocate everything and set kernel attributes before capture begins
+  int rc = evaluate(ctx, g->eb, s, base_map, (size_t)base_stride, n_cand, base_stride ? nullptr : offsets,
+                    base_stride ? nullptr : cells, reinterpret_cast<double2*>(S_out), fom_out, status, argmin_out,
+                    n_max_active);
+  if (rc == PXD_OK) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) rc = ctx->hip_fail(e, "hipStreamBeginCapture");
+  }
+  if (rc == PXD_OK) {
+    rc = evaluate(ctx, g->eb, s, base_map, (size_t)base_stride, n_cand, base_stride ? nullptr : offsets,
+                  base_stride ? nullptr : cells, reinterpret_cast<double2*>(S_out), fom_out, status, argmin_out,
+                  n_max_active, true);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc == PXD_OK && e != hipSuccess) rc = ctx->hip_fail(e, "hipStreamEndCapture");
+    g->graph = graph;
+    if (rc == PXD_OK) {
+      e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) rc = ctx->hip_fail(e, "hipGraphInstantiate");
+    }
+  }
+  if (rc != PXD_OK) {
+    pxd_graph_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return PXD_OK;
+}
+
+int pxd_graph_launch(pxd_graph* g, void* stream) {
+  if (!g || !g->exec) return pxd::set_thread_error(PXD_EINVAL, "graph is NULL");
+  pxd_ctx* ctx = g->ctx;
+  HIPCHK(ctx, hipSetDevice(ctx->opt.device));
+  hipStream_t s = static_cast<hipStream_t>(stream);  // NULL is the default stream
+  HIPCHK(ctx, hipGraphLaunch(g->exec, s));
+  return PXD_OK;
+}
+
+void pxd_graph_destroy(pxd_graph* g) {
+  if (!g) return;
+  if (g->ctx) {
+    (void)hipSetDevice(g->ctx->opt.device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    (void)hipDeviceSynchronize();
+  }
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->eb.release();
+  delete g;
 }
 
 int pxd_expand(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets, const int32_t* cells,
@@ -406,16 +653,16 @@ int pxd_expand(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int3
   HIPCHK(ctx, ctx->base.ensure(ctx->n_cells));
   HIPCHK(ctx, ctx->off.ensure(sizeof(int) * (C + 1)));
   HIPCHK(ctx, ctx->cells.ensure(sizeof(int) * std::max(1, nf)));
-  HIPCHK(ctx, ctx->Nc.ensure(sizeof(int) * C));
-  HIPCHK(ctx, ctx->Ilist.ensure(sizeof(int) * (size_t)C * ctx->M));
+  HIPCHK(ctx, ctx->eb.Nc.ensure(sizeof(int) * C));
+  HIPCHK(ctx, ctx->eb.Ilist.ensure(sizeof(int) * (size_t)C * ctx->M));
   HIPCHK(ctx, hipMemcpyAsync(ctx->base.p, base_map, ctx->n_cells, hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipMemcpyAsync(ctx->off.p, offsets, sizeof(int) * (C + 1), hipMemcpyHostToDevice, s));
   if (nf > 0) HIPCHK(ctx, hipMemcpyAsync(ctx->cells.p, cells, sizeof(int) * nf, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, pxd::launch_expand(s, ctx->base.as<uint8_t>(), ctx->n_cells, ctx->off.as<int>(), ctx->cells.as<int>(), C,
-                                 ctx->cell_a.as<int>(), ctx->cell_b.as<int>(), ctx->M, ctx->Nc.as<int>(),
-                                 ctx->Ilist.as<int>()));
-  HIPCHK(ctx, hipMemcpyAsync(N_out, ctx->Nc.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipMemcpyAsync(idx_out, ctx->Ilist.p, sizeof(int) * (size_t)C * ctx->M, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, pxd::launch_expand(s, ctx->base.as<uint8_t>(), ctx->n_cells, 0, ctx->off.as<int>(), ctx->cells.as<int>(),
+                                 C, ctx->cell_a.as<int>(), ctx->cell_b.as<int>(), ctx->M, ctx->eb.Nc.as<int>(),
+                                 ctx->eb.Ilist.as<int>()));
+  HIPCHK(ctx, hipMemcpyAsync(N_out, ctx->eb.Nc.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipMemcpyAsync(idx_out, ctx->eb.Ilist.p, sizeof(int) * (size_t)C * ctx->M, hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
   return PXD_OK;
 }
@@ -461,7 +708,7 @@ int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out) {
     if (ctx->stats_pending_counts && hipEventElapsedTime(&d, ctx->ev[2], ctx->ev[3]) == hipSuccess) {
       out->ms_fallback = d;
       int h[4] = {0, 0, 0, 0};
-      if (hipMemcpy(h, ctx->counter.p, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
+      if (hipMemcpy(h, ctx->eb.counter.p, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
         out->fallbacks = h[1];
         out->ir_iterations = h[2];
       }

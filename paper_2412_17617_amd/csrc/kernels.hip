@@ -46,7 +46,7 @@ struct LuShared {
 
 // ------------------------------------------------------------------ expand
 
-__global__ __launch_bounds__(256) void k_expand(const uint8_t* __restrict__ base, int n_cells,
+__global__ __launch_bounds__(256) void k_expand(const uint8_t* __restrict__ base, int n_cells, size_t base_stride,
                                                 const int* __restrict__ off, const int* __restrict__ cells,
                                                 const int* __restrict__ cell_a, const int* __restrict__ cell_b,
                                                 int M, int* __restrict__ Nc, int* __restrict__ Ilist) {
@@ -54,9 +54,10 @@ __global__ __launch_bounds__(256) void k_expand(const uint8_t* __restrict__ base
   __shared__ int wave_tot[4];
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int i = tid; i < n_cells; i += 256) smap[i] = base[i] ? 1 : 0;
+  const uint8_t* cmap = base + (size_t)c * base_stride;  // stride 0: one base map for every candidate
+  for (int i = tid; i < n_cells; i += 256) smap[i] = cmap[i] ? 1 : 0;
   __syncthreads();
-  if (tid == 0)
+  if (tid == 0 && off)  // no flip list: the candidate is its own map
     for (int i = off[c]; i < off[c + 1]; ++i) {
       const int cell = cells[i];
       if (cell >= 0 && cell < n_cells) smap[cell] ^= 1;
@@ -544,6 +545,25 @@ __device__ __forceinline__ int port_solve_and_s(const double2* __restrict__ W, i
 
 // ------------------------------------------------------------------ evaluator (FP64)
 
+// Item index -> (candidate, frequency).  Frequency-major: all candidates of
+// one frequency (largest first) before the next frequency, so concurrent
+// workgroups gather from the same parent.  Size-major: all frequencies of the
+// largest candidate first (longest-processing-time order for uneven batches).
+__device__ __forceinline__ void decode_item(const EvalParams& p, int it, int& c, int& f) {
+  if (p.item_list) {
+    const int e = p.item_list[it];
+    c = e / p.F;
+    f = e - c * p.F;
+  } else if (p.schedule == PXD_SCHED_SIZE_MAJOR) {
+    const int r = it / p.F;
+    f = it - r * p.F;
+    c = p.order[r];
+  } else {
+    f = it / p.C;
+    c = p.order[it - f * p.C];
+  }
+}
+
 template <int Q, int SB>
 __global__ __launch_bounds__(kThreads, 2) void k_eval_plain(EvalParams p) {
   using T = double2;
@@ -561,18 +581,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_plain(EvalParams p) {
     __syncthreads();
     if (it >= n_items) break;
     int c, f;
-    if (p.item_list) {
-      const int e = p.item_list[it];
-      c = e / p.F;
-      f = e - c * p.F;
-    } else {
-      f = it / p.C;
-      c = p.order[it - f * p.C];
-    }
+    decode_item(p, it, c, f);
     const int N = p.Nc[c];
     double2* Sout = p.S + ((size_t)c * p.F + f) * p.P * p.P;
-    if (N > kThreads * Q || N > p.nmax || N < p.P) {  // cannot happen when the host sizes the launch
-      if (tid == 0) p.status[(size_t)c * p.F + f] = PXD_STATUS_NONFINITE;
+    if (N > kThreads * Q || N > p.nmax || N < p.P) {  // outside the size the launch was built for
+      if (tid == 0) p.status[(size_t)c * p.F + f] = PXD_STATUS_SIZE;
       continue;
     }
     for (int s = tid; s < N; s += kThreads) sI[s] = p.Ilist[(size_t)c * p.M + s];
@@ -799,12 +812,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
     const int it = s_item;
     __syncthreads();
     if (it >= p.n_items) break;
-    const int f = it / p.C;
-    const int c = p.order[it - f * p.C];
+    int c, f;
+    decode_item(p, it, c, f);
     const int N = p.Nc[c];
     double2* Sout = p.S + ((size_t)c * p.F + f) * P * P;
     if (N > kThreads * Q || N > p.nmax || N < P) {
-      if (tid == 0) p.status[(size_t)c * p.F + f] = PXD_STATUS_NONFINITE;
+      if (tid == 0) p.status[(size_t)c * p.F + f] = PXD_STATUS_SIZE;
       continue;
     }
     for (int s = tid; s < N; s += kThreads) sI[s] = p.Ilist[(size_t)c * p.M + s];
@@ -929,11 +942,11 @@ __global__ void k_argmin(const double* __restrict__ fom, int C, int* __restrict_
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_expand(hipStream_t s, const uint8_t* base, int n_cells, const int* off, const int* cells, int C,
-                         const int* cell_a, const int* cell_b, int M, int* Nc, int* Ilist) {
+hipError_t launch_expand(hipStream_t s, const uint8_t* base, int n_cells, size_t base_stride, const int* off,
+                         const int* cells, int C, const int* cell_a, const int* cell_b, int M, int* Nc, int* Ilist) {
   if (C <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_expand, dim3(C), dim3(256), (size_t)n_cells, s, base, n_cells, off, cells, cell_a, cell_b, M,
-                     Nc, Ilist);
+  hipLaunchKernelGGL(k_expand, dim3(C), dim3(256), (size_t)n_cells, s, base, n_cells, base_stride, off, cells, cell_a,
+                     cell_b, M, Nc, Ilist);
   return hipGetLastError();
 }
 
@@ -949,37 +962,56 @@ hipError_t launch_fill_int(hipStream_t s, int* p, int n, int v) {
   return hipGetLastError();
 }
 
-hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid) {
-  const int Q = rows_per_thread(p.nmax);
-  if (Q <= 1)
-    hipLaunchKernelGGL((k_eval_plain<1, 16>), dim3(grid), dim3(kThreads), 0, s, p);
-  else if (Q <= 2)
-    hipLaunchKernelGGL((k_eval_plain<2, 8>), dim3(grid), dim3(kThreads), 0, s, p);
-  else if (Q <= 4)
-    hipLaunchKernelGGL((k_eval_plain<4, 4>), dim3(grid), dim3(kThreads), 0, s, p);
-  else if (Q <= 8)
-    hipLaunchKernelGGL((k_eval_plain<8, 2>), dim3(grid), dim3(kThreads), 0, s, p);
-  else
-    return hipErrorInvalidValue;
+// Sub-panel width of a variant: the full register budget (Q SB = 16) or half of it.
+template <int Q>
+constexpr int sb_of(int half) { return half ? (16 / Q > 1 ? 8 / Q : 1) : 16 / Q; }
+
+template <int Q, int SB>
+static hipError_t launch_plain_variant(hipStream_t s, const EvalParams& p, int grid) {
+  hipLaunchKernelGGL((k_eval_plain<Q, SB>), dim3(grid), dim3(kThreads), 0, s, p);
   return hipGetLastError();
+}
+
+hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid, int half_sb) {
+  const int Q = rows_per_thread(p.nmax);
+  if (Q <= 1) return half_sb ? launch_plain_variant<1, sb_of<1>(1)>(s, p, grid) : launch_plain_variant<1, sb_of<1>(0)>(s, p, grid);
+  if (Q <= 2) return half_sb ? launch_plain_variant<2, sb_of<2>(1)>(s, p, grid) : launch_plain_variant<2, sb_of<2>(0)>(s, p, grid);
+  if (Q <= 4) return half_sb ? launch_plain_variant<4, sb_of<4>(1)>(s, p, grid) : launch_plain_variant<4, sb_of<4>(0)>(s, p, grid);
+  if (Q <= 8) return half_sb ? launch_plain_variant<8, sb_of<8>(1)>(s, p, grid) : launch_plain_variant<8, sb_of<8>(0)>(s, p, grid);
+  return hipErrorInvalidValue;
+}
+
+template <int Q, int SB>
+static hipError_t prepare_mixed_variant(size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval_mixed<Q, SB>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <int Q, int SB>
 static hipError_t launch_mixed_variant(hipStream_t s, const EvalParams& p, int grid, size_t lds) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval_mixed<Q, SB>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_eval_mixed<Q, SB>), dim3(grid), dim3(kThreads), lds, s, p);
   return hipGetLastError();
 }
 
-hipError_t launch_eval_mixed(hipStream_t s, const EvalParams& p, int grid) {
+// Raise the dynamic LDS limit of the mixed kernel variant the launch will use
+// (host-side attribute; called outside any stream capture).
+hipError_t prepare_eval_mixed(const EvalParams& p, int half_sb) {
   const int Q = rows_per_thread(p.nmax);
   const size_t lds = eval_mixed_lds(p.nmax, p.P);
-  if (Q <= 1) return launch_mixed_variant<1, 16>(s, p, grid, lds);
-  if (Q <= 2) return launch_mixed_variant<2, 8>(s, p, grid, lds);
-  if (Q <= 4) return launch_mixed_variant<4, 4>(s, p, grid, lds);
-  if (Q <= 8) return launch_mixed_variant<8, 2>(s, p, grid, lds);
+  if (Q <= 1) return half_sb ? prepare_mixed_variant<1, sb_of<1>(1)>(lds) : prepare_mixed_variant<1, sb_of<1>(0)>(lds);
+  if (Q <= 2) return half_sb ? prepare_mixed_variant<2, sb_of<2>(1)>(lds) : prepare_mixed_variant<2, sb_of<2>(0)>(lds);
+  if (Q <= 4) return half_sb ? prepare_mixed_variant<4, sb_of<4>(1)>(lds) : prepare_mixed_variant<4, sb_of<4>(0)>(lds);
+  if (Q <= 8) return half_sb ? prepare_mixed_variant<8, sb_of<8>(1)>(lds) : prepare_mixed_variant<8, sb_of<8>(0)>(lds);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_eval_mixed(hipStream_t s, const EvalParams& p, int grid, int half_sb) {
+  const int Q = rows_per_thread(p.nmax);
+  const size_t lds = eval_mixed_lds(p.nmax, p.P);
+  if (Q <= 1) return half_sb ? launch_mixed_variant<1, sb_of<1>(1)>(s, p, grid, lds) : launch_mixed_variant<1, sb_of<1>(0)>(s, p, grid, lds);
+  if (Q <= 2) return half_sb ? launch_mixed_variant<2, sb_of<2>(1)>(s, p, grid, lds) : launch_mixed_variant<2, sb_of<2>(0)>(s, p, grid, lds);
+  if (Q <= 4) return half_sb ? launch_mixed_variant<4, sb_of<4>(1)>(s, p, grid, lds) : launch_mixed_variant<4, sb_of<4>(0)>(s, p, grid, lds);
+  if (Q <= 8) return half_sb ? launch_mixed_variant<8, sb_of<8>(1)>(s, p, grid, lds) : launch_mixed_variant<8, sb_of<8>(0)>(s, p, grid, lds);
   return hipErrorInvalidValue;
 }
 

@@ -36,6 +36,7 @@ struct EvalParams {
   int ld;               // leading dimension of the slot matrix
   int ir_max;
   double ir_tol;
+  int schedule;         // PXD_SCHED_FREQ_MAJOR or PXD_SCHED_SIZE_MAJOR (implicit order only)
 };
 
 // Per-slot layout of the workspace (byte offsets).
@@ -68,12 +69,14 @@ __host__ __device__ inline SlotLayout slot_layout(int nmax, int P, bool mixed) {
 // Rows of the register-resident sub-panel per thread for a given active size.
 __host__ __device__ inline int rows_per_thread(int nmax) { return (nmax + 255) / 256; }
 
-hipError_t launch_expand(hipStream_t s, const uint8_t* base, int n_cells, const int* off, const int* cells, int C,
-                         const int* cell_a, const int* cell_b, int M, int* Nc, int* Ilist);
+hipError_t launch_expand(hipStream_t s, const uint8_t* base, int n_cells, size_t base_stride, const int* off,
+                         const int* cells, int C, const int* cell_a, const int* cell_b, int M, int* Nc, int* Ilist);
 hipError_t launch_order(hipStream_t s, const int* Nc, int C, int* order);
 hipError_t launch_fill_int(hipStream_t s, int* p, int n, int v);
-hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid);
-hipError_t launch_eval_mixed(hipStream_t s, const EvalParams& p, int grid);
+// half_sb selects the variant whose register sub-panel is half as wide.
+hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid, int half_sb);
+hipError_t prepare_eval_mixed(const EvalParams& p, int half_sb);
+hipError_t launch_eval_mixed(hipStream_t s, const EvalParams& p, int grid, int half_sb);
 // dynamic LDS of the mixed evaluator for a given largest active size and port count
 size_t eval_mixed_lds(int nmax, int P);
 hipError_t launch_fom(hipStream_t s, const double2* S, int C, int F, int P, const pxd_fom_term* terms,

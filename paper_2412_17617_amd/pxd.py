@@ -18,7 +18,8 @@ LIB_PATH = os.environ.get("PXD_LIB_PATH") or os.path.join(_HERE, "libpxd.so")
 OK, EINVAL, ENOMEM, ENOTLOADED, EDEVICE, ESHAPE = 0, -1, -2, -3, -4, -5
 PREC_FP64, PREC_MIXED32 = 0, 1
 KIND_ALWAYS, KIND_INNER, KIND_INTER, KIND_PIXPORT, KIND_VIA = 0, 1, 2, 3, 4
-STATUS_OK, STATUS_FALLBACK, STATUS_NONFINITE, STATUS_SINGULAR = 0, 1, -1, -2
+STATUS_OK, STATUS_FALLBACK, STATUS_NONFINITE, STATUS_SINGULAR, STATUS_SIZE = 0, 1, -1, -2, -3
+SCHED_AUTO, SCHED_FREQ_MAJOR, SCHED_SIZE_MAJOR = 0, 1, 2
 SIDES = {"right": 0, "top": 1, "left": 2, "bottom": 3}
 
 
@@ -40,7 +41,7 @@ class Geometry(C.Structure):
 class Options(C.Structure):
     _fields_ = [
         ("device", C.c_int32), ("precision", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
-        ("wg_per_cu", C.c_int32), ("panel", C.c_int32),
+        ("wg_per_cu", C.c_int32), ("half_subpanel", C.c_int32), ("schedule", C.c_int32),
     ]
 
 
@@ -55,6 +56,11 @@ class Stats(C.Structure):
         ("max_active", C.c_int32), ("min_active", C.c_int32),
         ("ms_expand", C.c_double), ("ms_solve", C.c_double), ("ms_fallback", C.c_double), ("ms_fom", C.c_double),
     ]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("rows_per_thread", C.c_int32), ("wg_per_cu", C.c_int32), ("half_subpanel", C.c_int32),
+                ("schedule", C.c_int32), ("ms", C.c_double)]
 
 
 _VP = C.c_void_p
@@ -76,6 +82,15 @@ _SIGS = {
     "pxd_expand": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "pxd_gather": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP]),
     "pxd_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
+    "pxd_evaluate_maps": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    "pxd_evaluate_maps_device": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    "pxd_autotune": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, C.c_int32, _VP]),
+    "pxd_tune_save": (C.c_int, [_VP, C.c_char_p]),
+    "pxd_tune_load": (C.c_int, [_VP, C.c_char_p]),
+    "pxd_graph_create": (C.c_int, [_VP, _VP, C.c_int64, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP,
+                                   C.POINTER(_VP)]),
+    "pxd_graph_launch": (C.c_int, [_VP, _VP]),
+    "pxd_graph_destroy": (None, [_VP]),
 }
 
 _lib_handle = None
@@ -85,6 +100,15 @@ def lib():
     """Load libpxd.so (built by ``python -m paper_2412_17617_amd.build``)."""
     global _lib_handle
     if _lib_handle is None:
+        # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7
+        # under the same soname as the system one the library links.  Loading
+        # torch first makes the library bind to torch's copy, so device
+        # pointers and streams from torch are valid here; loaded the other
+        # way round, torch would run on a runtime it was not built for.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2412_17617_amd.build")
         h = C.CDLL(LIB_PATH)
@@ -161,8 +185,9 @@ class Problem:
 class Evaluator:
     """GPU evaluator context (one per device and host thread)."""
 
-    def __init__(self, device=0, precision=PREC_FP64, ir_max_iter=10, ir_tol=1e-7, wg_per_cu=0, panel=0):
-        o = Options(device, precision, ir_max_iter, ir_tol, wg_per_cu, panel)
+    def __init__(self, device=0, precision=PREC_FP64, ir_max_iter=10, ir_tol=1e-7, wg_per_cu=0, half_subpanel=0,
+                 schedule=SCHED_AUTO):
+        o = Options(device, precision, ir_max_iter, ir_tol, wg_per_cu, half_subpanel, schedule)
         h_ = _VP()
         _check(lib().pxd_create(C.byref(o), C.byref(h_)))
         self._h = h_
@@ -228,6 +253,53 @@ class Evaluator:
                                                 cells.numel(), dp(S_out), dp(fom_out), dp(status_out),
                                                 dp(argmin_out)))
 
+    def evaluate_maps(self, maps, want_S=True):
+        """Candidates given as whole maps (n_maps x n_cells uint8)."""
+        maps = np.ascontiguousarray(maps, np.uint8)
+        n = maps.shape[0]
+        assert maps.ndim == 2 and maps.shape[1] == self.n_cells
+        S = np.empty((n, self.F, self.P, self.P), np.complex128) if want_S else None
+        fom = np.empty(n, np.float64)
+        st = np.empty(n, np.int32)
+        am = np.zeros(1, np.int32)
+        self._c(lib().pxd_evaluate_maps(self._h, n, _ptr(maps), _ptr(S), _ptr(fom), _ptr(st), _ptr(am)))
+        return S, fom, st, int(am[0])
+
+    def evaluate_maps_device(self, stream, maps, S_out, fom_out, status_out=None, argmin_out=None):
+        sp = getattr(stream, "cuda_stream", stream)
+
+        def dp(t):
+            return None if t is None else _VP(t.data_ptr())
+
+        self._c(lib().pxd_evaluate_maps_device(self._h, _VP(sp), maps.shape[0], dp(maps), dp(S_out), dp(fom_out),
+                                               dp(status_out), dp(argmin_out)))
+
+    def autotune(self, base_map, offsets, cells, n_reps=1):
+        """Time every launch configuration on this batch; the fastest becomes
+        the context's choice for its precision and size class.  Returns the
+        tried configurations, fastest first."""
+        base = np.ascontiguousarray(base_map, np.uint8)
+        off = np.ascontiguousarray(offsets, np.int32)
+        cl = np.ascontiguousarray(cells, np.int32)
+        rep = (TuneEntry * 16)()
+        n = C.c_int32()
+        self._c(lib().pxd_autotune(self._h, _ptr(base), len(off) - 1, _ptr(off),
+                                   _ptr(cl if len(cl) else np.zeros(1, np.int32)), n_reps, C.cast(rep, _VP), 16,
+                                   C.byref(n)))
+        return [{k: getattr(rep[i], k) for k, _ in TuneEntry._fields_} for i in range(n.value)]
+
+    def tune_save(self, path):
+        self._c(lib().pxd_tune_save(self._h, os.fsencode(path)))
+
+    def tune_load(self, path):
+        self._c(lib().pxd_tune_load(self._h, os.fsencode(path)))
+
+    def graph(self, base_map, offsets, cells, n_max_active, S_out, fom_out, status_out=None, argmin_out=None,
+              maps=False):
+        """Capture the device-side evaluation of this batch (torch CUDA
+        tensors) into a HIP graph; returns a Graph to launch repeatedly."""
+        return Graph(self, base_map, offsets, cells, n_max_active, S_out, fom_out, status_out, argmin_out, maps)
+
     def expand(self, base_map, offsets, cells):
         base = np.ascontiguousarray(base_map, np.uint8)
         off = np.ascontiguousarray(offsets, np.int32)
@@ -253,6 +325,40 @@ class Evaluator:
     def close(self):
         if getattr(self, "_h", None) and _lib_handle is not None:
             _lib_handle.pxd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Graph:
+    """A captured evaluation (pxd_graph_*).  Holds references to the tensors it
+    reads and writes so they outlive it."""
+
+    def __init__(self, ev, base_map, offsets, cells, n_max_active, S_out, fom_out, status_out, argmin_out, maps):
+        def dp(t):
+            return None if t is None else _VP(t.data_ptr())
+
+        self._ev = ev
+        self._keep = (base_map, offsets, cells, S_out, fom_out, status_out, argmin_out)
+        if maps:
+            n, stride = base_map.shape[0], base_map.shape[1]
+            off_p, cells_p = None, None
+        else:
+            n, stride = offsets.numel() - 1, 0
+            off_p, cells_p = dp(offsets), dp(cells)
+        h_ = _VP()
+        ev._c(lib().pxd_graph_create(ev._h, dp(base_map), stride, n, off_p, cells_p, n_max_active, dp(S_out),
+                                     dp(fom_out), dp(status_out), dp(argmin_out), C.byref(h_)))
+        self._h = h_
+
+    def launch(self, stream=None):
+        sp = 0 if stream is None else getattr(stream, "cuda_stream", stream)
+        _check(lib().pxd_graph_launch(self._h, _VP(sp)))
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib_handle is not None:
+            _lib_handle.pxd_graph_destroy(self._h)
             self._h = None
 
     def __del__(self):

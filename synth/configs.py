@@ -90,6 +90,18 @@ class WorkloadSpec:
             out.append((m, off, cl))
         return out
 
+    def uneven_maps(self, n_maps: int = 8, per_map: int = 100, p0: float = 0.55, dp: float = 0.04) -> np.ndarray:
+        """The uneven batch as whole maps, one row per candidate (base map
+        with its cell toggled), in batch order."""
+        rows = []
+        for m, off, cl in self.uneven_batch(n_maps, per_map, p0, dp):
+            for c in range(len(off) - 1):
+                r = m.copy()
+                for cell in cl[off[c]:off[c + 1]]:
+                    r[cell] ^= 1
+                rows.append(r)
+        return np.array(rows, dtype=np.uint8).reshape(len(rows), self.n_cells)
+
 
 def _p(*pairs):
     return tuple(PortSpec(s, l) for s, l in pairs)

