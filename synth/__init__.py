@@ -7,7 +7,7 @@ function classification, no Green's function, no solve, no S-parameters, no
 figure of merit.  Both sides import it; neither side's code lives here.
 """
 
-from .rng import SplitMix64, bernoulli_map, permutation, single_flips, pair_flips_3x3
+from .rng import SplitMix64, bernoulli_map, permutation, single_flips, pair_flips_3x3, uniform_array
 from .configs import WorkloadSpec, PortSpec, get_spec, SPECS
 
 __all__ = [
@@ -16,6 +16,7 @@ __all__ = [
     "permutation",
     "single_flips",
     "pair_flips_3x3",
+    "uniform_array",
     "WorkloadSpec",
     "PortSpec",
     "get_spec",

@@ -84,3 +84,12 @@ def pair_flips_3x3(n_layers: int, nx: int, ny: int) -> tuple[np.ndarray, np.ndar
     cells = np.array(pairs, dtype=np.int32).reshape(-1)
     offsets = np.arange(0, 2 * len(pairs) + 1, 2, dtype=np.int32)
     return offsets, cells
+
+
+def uniform_array(n: int, seed: int, bound: float) -> np.ndarray:
+    """n draws uniform in [-bound, bound) from SplitMix64(seed), as float64."""
+    g = SplitMix64(seed)
+    out = np.empty(n, np.float64)
+    for i in range(n):
+        out[i] = (2.0 * g.next_unit() - 1.0) * bound
+    return out
