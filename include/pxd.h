@@ -242,6 +242,82 @@ int pxd_graph_create(pxd_ctx* ctx, const uint8_t* base_map, int64_t base_stride,
 int pxd_graph_launch(pxd_graph* g, void* stream);
 void pxd_graph_destroy(pxd_graph* g);
 
+/* ------------------------------------------------------------ CNN surrogate
+ *
+ * A small convolutional network that predicts, from a pixel map and a
+ * frequency, the S entries the FoM of Eqs. 8-9 weighs most, so that a search
+ * step of Algorithm 1 can rank every candidate and solve only the best k
+ * exactly (the exact solve remains the judge of every accepted flip).  It is
+ * not part of the paper's method.  Architecture (all kernels hand-written):
+ *   x0   = map as an image (channels = layers; cell l*ny*nx + y*nx + x)
+ *   a1   = relu(conv3x3(x0)),  a2 = pool2(relu(conv3x3(a1))),
+ *   a3   = relu(conv3x3(a2)),  a4 = pool2(relu(conv3x3(a3)))
+ *   h    = relu(flatten(a4) Wf + e(u) We + bh),  out = h Wo + bo
+ * conv3x3: zero padding 1, weights [tap = 3 dy + dx][c_in][c_out] applied to
+ * x[y + dy - 1][x + dx - 1]; pool2: 2 x 2 mean, odd last row/column dropped;
+ * flatten order (y, x, channel); e(u)_{2j} = sin((j+1) pi u),
+ * e(u)_{2j+1} = cos((j+1) pi u), u = (f - f_lo) / (f_hi - f_lo).
+ * Outputs per (map, frequency) and predicted entry, in entry order: ln|S|
+ * and the unit phasor (cos arg S, sin arg S), so S = |S| (cos + j sin); the
+ * squared error on ln|S| weighs relative error alike for large and tiny
+ * entries, as the FoM's powers of |S| do.  Parameters: one float32 vector, tensors in the order W1 b1 W2 b2 W3
+ * b3 W4 b4 Wf We bh Wo bo, each row-major in the shapes above.
+ * The products run on MFMA: FP32 (16x16x4) or BF16 operands with FP32
+ * accumulation (16x16x16); parameters, activations and gradients are kept in
+ * FP32.  Loss: mean squared error over all outputs.  Optimiser: AdamW with
+ * bias-corrected moments, decay on every parameter. */
+
+#define PXD_SUR_FP32 0
+#define PXD_SUR_BF16 1
+
+typedef struct pxd_sur_config {
+  int32_t device;
+  int32_t n_layers, ny, nx;  /* map shape */
+  int32_t channels[4];       /* conv widths (e.g. 32 32 64 64), each <= 256 */
+  int32_t hidden, emb;       /* head width; frequency embedding size (even) */
+  int32_t n_entries;         /* predicted S entries, 1..4: (entry_i[k], entry_j[k]), 0-based */
+  int32_t entry_i[4], entry_j[4];
+  int32_t precision;         /* PXD_SUR_* */
+  int32_t max_batch;         /* largest number of maps per call */
+} pxd_sur_config;
+
+typedef struct pxd_adamw {
+  double lr, beta1, beta2, eps, weight_decay;
+} pxd_adamw;
+
+typedef struct pxd_sur pxd_sur;
+
+/* freqs_hz: the F frequencies every map is evaluated at; f_lo, f_hi set u. */
+int pxd_sur_create(const pxd_sur_config* cfg, int32_t F, const double* freqs_hz, double f_lo, double f_hi,
+                   pxd_sur** out);
+void pxd_sur_destroy(pxd_sur* s);
+const char* pxd_sur_last_error(const pxd_sur* s);
+int pxd_sur_num_params(const pxd_sur* s, int64_t* n);
+/* Uniform initialisation from SplitMix64(seed * 1000 + tensor index): weights
+ * in +-sqrt(3 / fan_in) (fan_in = product of all but the last dimension),
+ * biases in +-0.05.  Resets the optimiser state. */
+int pxd_sur_init_params(pxd_sur* s, uint64_t seed);
+/* Host float32 vectors of length num_params. set resets the optimiser state. */
+int pxd_sur_set_params(pxd_sur* s, const float* params, int64_t n);
+int pxd_sur_get_params(const pxd_sur* s, float* params, int64_t n);
+/* Device pointers on `stream`: maps B x n_cells uint8 (0/1); out and target
+ * B x F x (3 n_entries) float32. */
+int pxd_sur_forward(pxd_sur* s, void* stream, int32_t B, const uint8_t* maps, float* out);
+/* Loss (device float, may be NULL) and its gradient (device float32
+ * num_params, may be NULL: kept inside) without updating the parameters. */
+int pxd_sur_gradient(pxd_sur* s, void* stream, int32_t B, const uint8_t* maps, const float* target, float* grad,
+                     float* loss);
+/* Gradient then one AdamW step. */
+int pxd_sur_train_step(pxd_sur* s, void* stream, int32_t B, const uint8_t* maps, const float* target,
+                       const pxd_adamw* hp, float* loss);
+/* Rank candidates (base map + CSR flips, device pointers as in
+ * pxd_evaluate_flips_device) by the FoM of the predicted |S| = exp(ln|S|),
+ * using the FoM table of `ctx` (terms on entries the network does not
+ * predict are left out).  fom_pred: n_cand doubles (device); top: the k lowest, best first,
+ * ties to the lower index (device int32). */
+int pxd_sur_rank(pxd_sur* s, const pxd_ctx* ctx, void* stream, const uint8_t* base_map, int32_t n_cand,
+                 const int32_t* offsets, const int32_t* cells, int32_t k, double* fom_pred, int32_t* top);
+
 #ifdef __cplusplus
 }
 #endif

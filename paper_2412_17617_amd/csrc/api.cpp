@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 #include "pxd.h"
 #include "status.hpp"
+#include "surrogate.hpp"
 
 namespace {
 
@@ -277,6 +278,19 @@ int download(pxd_ctx* ctx, int C, double* S_out, double* fom_out, int32_t* statu
 }
 
 }  // namespace
+
+namespace pxd {
+int fom_table(const pxd_ctx* ctx, FomTable* out) {
+  if (!ctx || !ctx->terms.p) return PXD_ENOTLOADED;
+  out->terms = ctx->terms.as<pxd_fom_term>();
+  out->term_fac = ctx->term_fac.as<double>();
+  out->band = ctx->band.as<int8_t>();
+  out->n_terms = ctx->n_terms;
+  out->F = ctx->F;
+  out->P = ctx->P;
+  return PXD_OK;
+}
+}  // namespace pxd
 
 extern "C" {
 

@@ -363,3 +363,119 @@ class Graph:
 
     def __del__(self):
         self.close()
+
+
+SUR_FP32, SUR_BF16 = 0, 1
+
+
+class SurConfig(C.Structure):
+    _fields_ = [
+        ("device", C.c_int32), ("n_layers", C.c_int32), ("ny", C.c_int32), ("nx", C.c_int32),
+        ("channels", C.c_int32 * 4), ("hidden", C.c_int32), ("emb", C.c_int32), ("n_entries", C.c_int32),
+        ("entry_i", C.c_int32 * 4), ("entry_j", C.c_int32 * 4), ("precision", C.c_int32), ("max_batch", C.c_int32),
+    ]
+
+
+class AdamW(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("weight_decay", C.c_double)]
+
+
+_SIGS.update({
+    "pxd_sur_create": (C.c_int, [C.POINTER(SurConfig), C.c_int32, _VP, C.c_double, C.c_double, C.POINTER(_VP)]),
+    "pxd_sur_destroy": (None, [_VP]),
+    "pxd_sur_last_error": (C.c_char_p, [_VP]),
+    "pxd_sur_num_params": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "pxd_sur_init_params": (C.c_int, [_VP, C.c_uint64]),
+    "pxd_sur_set_params": (C.c_int, [_VP, _VP, C.c_int64]),
+    "pxd_sur_get_params": (C.c_int, [_VP, _VP, C.c_int64]),
+    "pxd_sur_forward": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP]),
+    "pxd_sur_gradient": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "pxd_sur_train_step": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, C.POINTER(AdamW), _VP]),
+    "pxd_sur_rank": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP]),
+})
+
+
+class Surrogate:
+    """CNN surrogate (pxd_sur_*).  Device arrays are torch CUDA tensors (or any
+    object with data_ptr()); stream is a torch.cuda.Stream, a raw handle or
+    None (HIP's default stream)."""
+
+    def __init__(self, n_layers, ny, nx, freqs, f_lo, f_hi, entries=((0, 0), (1, 0), (2, 0)),
+                 channels=(32, 32, 64, 64), hidden=256, emb=16, precision=SUR_BF16, max_batch=64, device=0):
+        c = SurConfig()
+        c.device, c.n_layers, c.ny, c.nx = device, n_layers, ny, nx
+        for i in range(4):
+            c.channels[i] = channels[i]
+        c.hidden, c.emb, c.n_entries = hidden, emb, len(entries)
+        for k, (i, j) in enumerate(entries):
+            c.entry_i[k], c.entry_j[k] = i, j
+        c.precision, c.max_batch = precision, max_batch
+        freqs = np.ascontiguousarray(freqs, np.float64)
+        h_ = _VP()
+        _check(lib().pxd_sur_create(C.byref(c), len(freqs), _ptr(freqs), f_lo, f_hi, C.byref(h_)))
+        self._h = h_
+        self.F, self.n_out, self.max_batch = len(freqs), 3 * len(entries), max_batch
+        n = C.c_int64()
+        self._c(lib().pxd_sur_num_params(self._h, C.byref(n)))
+        self.n_params = n.value
+
+    def _c(self, rc):
+        if rc != OK:
+            msg = lib().pxd_sur_last_error(self._h)
+            raise PxdError(rc, msg.decode() if msg else "")
+
+    @staticmethod
+    def _s(stream):
+        return _VP(0 if stream is None else getattr(stream, "cuda_stream", stream))
+
+    @staticmethod
+    def _d(t):
+        return None if t is None else _VP(t.data_ptr())
+
+    def init_params(self, seed):
+        self._c(lib().pxd_sur_init_params(self._h, seed))
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self._c(lib().pxd_sur_set_params(self._h, _ptr(p), len(p)))
+
+    def get_params(self):
+        p = np.empty(self.n_params, np.float32)
+        self._c(lib().pxd_sur_get_params(self._h, _ptr(p), len(p)))
+        return p
+
+    def forward(self, maps, out, stream=None):
+        self._c(lib().pxd_sur_forward(self._h, self._s(stream), maps.shape[0], self._d(maps), self._d(out)))
+
+    def gradient(self, maps, target, grad=None, loss=None, stream=None):
+        self._c(lib().pxd_sur_gradient(self._h, self._s(stream), maps.shape[0], self._d(maps), self._d(target),
+                                       self._d(grad), self._d(loss)))
+
+    def train_step(self, maps, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, loss=None,
+                   stream=None):
+        hp = AdamW(lr, beta1, beta2, eps, weight_decay)
+        self._c(lib().pxd_sur_train_step(self._h, self._s(stream), maps.shape[0], self._d(maps), self._d(target),
+                                         C.byref(hp), self._d(loss)))
+
+    def rank(self, evaluator, base_map, offsets, cells, k, fom_pred, top, stream=None):
+        self._c(lib().pxd_sur_rank(self._h, evaluator._h, self._s(stream), self._d(base_map), offsets.numel() - 1,
+                                   self._d(offsets), self._d(cells), k, self._d(fom_pred), self._d(top)))
+
+    @staticmethod
+    def encode(S, entries=((0, 0), (1, 0), (2, 0))):
+        """Training targets from S (..., P, P): per entry ln|S|, cos arg S, sin arg S."""
+        out = []
+        for i, j in entries:
+            v = S[..., i, j]
+            a = np.maximum(np.abs(v), 1e-30)
+            out += [np.log(a), v.real / a, v.imag / a]
+        return np.stack(out, axis=-1).astype(np.float32)
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib_handle is not None:
+            _lib_handle.pxd_sur_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
