@@ -66,6 +66,8 @@ extern "C" {
 /* Arithmetic of the dense solve. */
 #define PXD_PREC_FP64 0    /* complex128 LU, no refinement ("plain") */
 #define PXD_PREC_MIXED32 1 /* complex64 LU + FP64 residual and iterative refinement */
+#define PXD_PREC_MIXED_BF16 2 /* as MIXED32, the rank-64 block-column updates on BF16 operands (FP32 accumulation) */
+#define PXD_PREC_MIXED_F16 3  /* as MIXED32, the rank-64 block-column updates on FP16 operands (FP32 accumulation) */
 
 /* ---------------------------------------------------------------- structure */
 
@@ -114,9 +116,11 @@ typedef struct pxd_options {
   int32_t device;          /* HIP device ordinal */
   int32_t precision;       /* PXD_PREC_* */
   int32_t ir_max_iter;     /* refinement iterations before FP64 fallback (default 10) */
-  double ir_tol;           /* stop when the last correction changed no S entry by more than ir_tol
-                              (absolute, |dS_ij| = 2 Z0 l_i |d_i^(j)|; default 1e-7); the correction is
-                              applied, so the result is about ir_tol x the contraction factor accurate */
+  double ir_tol;           /* relative accuracy of every S entry at which refinement stops (default 1e-7):
+                              the error left after a step is estimated as rho / (1 - rho) times the largest
+                              change the step made to any S entry, rho the observed contraction (ratio of the last two
+                              largest changes, so at least two steps are taken), and must be below
+                              ir_tol |S_ij| + 1e-11 */
   int32_t wg_per_cu;       /* persistent workgroups per compute unit: 1 or 2 (0 = tuned, else 2) */
   int32_t half_subpanel;   /* register sub-panel of the LU: 1 full width, 2 half width (0 = tuned, else full) */
   int32_t schedule;        /* PXD_SCHED_* */
@@ -147,7 +151,7 @@ void pxd_destroy(pxd_ctx* ctx);
 const char* pxd_last_error(const pxd_ctx* ctx); /* ctx may be NULL: thread-local last error */
 
 /* Parent matrices: F x M x M complex128 row-major host array, frequencies in Hz.
- * The library keeps a device copy (and a complex64 copy in MIXED32 mode). */
+ * The library keeps a device copy (and a complex64 copy in the mixed modes). */
 int pxd_load_parent(pxd_ctx* ctx, int32_t M, int32_t F, const double* freqs_hz, const double* Z);
 
 /* Pixel-to-RWG map (Section II-C): per parent function its kind and the cells

@@ -59,6 +59,7 @@ struct Tuning {
   double ms = 0;
 };
 constexpr int kSizeClasses = 4;  // Q = 1, 2, 4, 8
+constexpr int kPrecisions = 4;   // PXD_PREC_*
 int size_class(int Q) { return Q <= 1 ? 0 : Q <= 2 ? 1 : Q <= 4 ? 2 : 3; }
 
 }  // namespace
@@ -88,7 +89,7 @@ struct pxd_ctx {
   pxd_stats stats{};
   bool stats_pending_counts = false;
   // autotuning: tuned[precision][size class]; `forced` overrides during a tuning sweep
-  Tuning tuned[2][kSizeClasses];
+  Tuning tuned[kPrecisions][kSizeClasses];
   const Tuning* forced = nullptr;
 
   int fail(int rc, const std::string& m) {
@@ -120,7 +121,7 @@ namespace {
 // options first, then the tuned table, then the defaults.
 Tuning resolve(const pxd_ctx* ctx, int Q) {
   if (ctx->forced) return *ctx->forced;
-  const Tuning& t = ctx->tuned[ctx->opt.precision == PXD_PREC_MIXED32][size_class(Q)];
+  const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(Q)];
   Tuning r = t.valid ? t : Tuning{};
   if (ctx->opt.wg_per_cu > 0) r.wg_per_cu = std::min(ctx->opt.wg_per_cu, 2);
   if (ctx->opt.half_subpanel == 1 || ctx->opt.half_subpanel == 2) r.half_sb = ctx->opt.half_subpanel - 1;
@@ -138,7 +139,7 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   if (!ctx->Z128.p) return ctx->fail(PXD_ENOTLOADED, "parent matrices not loaded");
   if (!ctx->cell_a.p) return ctx->fail(PXD_ENOTLOADED, "pixel-to-RWG map not loaded");
   if (!ctx->terms.p) return ctx->fail(PXD_ENOTLOADED, "FoM table not set");
-  const bool mixed = ctx->opt.precision == PXD_PREC_MIXED32;
+  const bool mixed = ctx->opt.precision != PXD_PREC_FP64;
   const bool events = !capturing;
   const int M = ctx->M, F = ctx->F, P = ctx->P;
   if (events) ctx->stats = pxd_stats{};
@@ -196,6 +197,8 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   ep.ir_max = ctx->opt.ir_max_iter;
   ep.ir_tol = ctx->opt.ir_tol;
   ep.schedule = tune.schedule;
+  ep.half = ctx->opt.precision == PXD_PREC_MIXED_BF16 ? PXD_HALF_BF16
+            : ctx->opt.precision == PXD_PREC_MIXED_F16 ? PXD_HALF_F16 : PXD_HALF_NONE;
   int* cnt = b.counter.as<int>();  // [0] work, [1] fallback count, [2] refinement steps, [3] fallback work
   ep.fb_list = b.fb_list.as<int>();
   ep.fb_count = cnt + 1;
@@ -304,7 +307,7 @@ int pxd_create(const pxd_options* opt, pxd_ctx** out) {
   if (opt) ctx->opt = *opt;
   if (ctx->opt.ir_max_iter <= 0) ctx->opt.ir_max_iter = 10;
   if (!(ctx->opt.ir_tol > 0)) ctx->opt.ir_tol = 1e-7;
-  if (ctx->opt.precision != PXD_PREC_FP64 && ctx->opt.precision != PXD_PREC_MIXED32) {
+  if (ctx->opt.precision < PXD_PREC_FP64 || ctx->opt.precision > PXD_PREC_MIXED_F16) {
     delete ctx;
     return pxd::set_thread_error(PXD_EINVAL, "unknown precision mode");
   }
@@ -355,7 +358,7 @@ int pxd_load_parent(pxd_ctx* ctx, int32_t M, int32_t F, const double* freqs_hz, 
   ctx->Z64.release();
   HIPCHK(ctx, ctx->Z128.ensure(n * 16));
   HIPCHK(ctx, hipMemcpyAsync(ctx->Z128.p, Z, n * 16, hipMemcpyHostToDevice, ctx->stream));
-  if (ctx->opt.precision == PXD_PREC_MIXED32) {
+  if (ctx->opt.precision != PXD_PREC_FP64) {
     HIPCHK(ctx, ctx->Z64.ensure(n * 8));
     HIPCHK(ctx, pxd::launch_to_c64(ctx->stream, ctx->Z128.as<double2>(), ctx->Z64.as<float2>(), n));
   }
@@ -536,7 +539,7 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
   std::stable_sort(tried.begin(), tried.end(),
                    [](const pxd_tune_entry& a, const pxd_tune_entry& b) { return a.ms < b.ms; });
   const pxd_tune_entry& w = tried.front();
-  Tuning& slot = ctx->tuned[ctx->opt.precision == PXD_PREC_MIXED32][size_class(Q)];
+  Tuning& slot = ctx->tuned[ctx->opt.precision][size_class(Q)];
   slot.wg_per_cu = w.wg_per_cu, slot.half_sb = w.half_subpanel, slot.schedule = w.schedule;
   slot.ms = w.ms, slot.valid = true;
   const int n = std::min<int>(max_report, (int)tried.size());
@@ -551,7 +554,7 @@ int pxd_tune_save(const pxd_ctx* ctx, const char* path) {
   if (!f) return pxd::set_thread_error(PXD_EINVAL, std::string("cannot write ") + path);
   std::fprintf(f, "# precision rows_per_thread wg_per_cu half_subpanel schedule ms\n");
   const int Qs[kSizeClasses] = {1, 2, 4, 8};
-  for (int prec = 0; prec < 2; ++prec)
+  for (int prec = 0; prec < kPrecisions; ++prec)
     for (int q = 0; q < kSizeClasses; ++q) {
       const Tuning& t = ctx->tuned[prec][q];
       if (t.valid) std::fprintf(f, "%d %d %d %d %d %.6f\n", prec, Qs[q], t.wg_per_cu, t.half_sb, t.schedule, t.ms);
@@ -570,7 +573,8 @@ int pxd_tune_load(pxd_ctx* ctx, const char* path) {
     if (line[0] == '#' || line[0] == '\n') continue;
     int prec, Q, wg, half, sched;
     double ms;
-    if (std::sscanf(line, "%d %d %d %d %d %lf", &prec, &Q, &wg, &half, &sched, &ms) != 6 || prec < 0 || prec > 1 ||
+    if (std::sscanf(line, "%d %d %d %d %d %lf", &prec, &Q, &wg, &half, &sched, &ms) != 6 || prec < 0 ||
+        prec >= kPrecisions ||
         (Q != 1 && Q != 2 && Q != 4 && Q != 8) || wg < 1 || wg > 2 || half < 0 || half > 1 ||
         sched < PXD_SCHED_FREQ_MAJOR || sched > PXD_SCHED_SIZE_MAJOR) {
       rc = ctx->fail(PXD_EINVAL, std::string("malformed tuning line: ") + line);

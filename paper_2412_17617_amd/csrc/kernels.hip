@@ -29,18 +29,22 @@
 
 namespace pxd {
 
-constexpr int NB = 32;
+constexpr int NB = 32;     // inner panel width
+constexpr int KBMAX = 128; // widest outer block column
+constexpr int CS = 32;     // column slab of the wide trailing update staged in LDS
+constexpr int KB_PLAIN = 64;  // block column of the complex128 LU
+constexpr int KB_MIXED = 64;  // block column of the complex64 LU
 
 template <typename R>
 struct LuShared {
   using T = typename Cx<R>::T;
   T prow[NB];
   T crow[NB];
-  T L11[NB * NB];
-  T Usub[NB * NB];
+  T buf[2 * NB * NB];  // L11 (first half) and the sub-panel U block (second half), or a wide-update slab
   R red_v[kWaves];
   int red_i[kWaves];
   int piv[NB];
+  int bpiv[KBMAX];  // pivots of the current block column (absolute rows)
   int bad;
 };
 
@@ -303,7 +307,7 @@ __device__ __forceinline__ void factor_panel(typename Cx<R>::T* __restrict__ W, 
         for (int i = 0; i < SB; ++i)
           if (i < sbw) {
             W[(size_t)(c0 + i) * ld + col] = u[i];
-            sm.Usub[i * NB + t] = u[i];
+            sm.buf[NB * NB + i * NB + t] = u[i];
           }
       }
       __syncthreads();
@@ -315,7 +319,7 @@ __device__ __forceinline__ void factor_panel(typename Cx<R>::T* __restrict__ W, 
         for (int t = 0; t < w2; ++t) {
           T acc = row[t];
 #pragma unroll
-          for (int j = 0; j < SB; ++j) acc = cfms(acc, l[j], sm.Usub[j * NB + t]);
+          for (int j = 0; j < SB; ++j) acc = cfms(acc, l[j], sm.buf[NB * NB + j * NB + t]);
           row[t] = acc;
         }
       }
@@ -324,29 +328,31 @@ __device__ __forceinline__ void factor_panel(typename Cx<R>::T* __restrict__ W, 
   }
 }
 
-// Interchanges of the panel on the trailing columns [k + kb, ncols), then
-// U12 = L11^-1 A12 (unit lower), one thread per column, in blocks of 8 rows
-// held in registers.
+// Interchanges of panel rows [k, k + kb) (pivots in piv, absolute rows; no
+// interchanges when piv is null) on columns [c0, c1), then U = L11^-1 A for
+// those rows and columns (L11 unit lower, from the panel), one thread per
+// column, in blocks of 8 rows held in registers.
 template <typename R>
-__device__ __forceinline__ void swap_trsm(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int ncols,
-                                          LuShared<R>& sm) {
+__device__ __forceinline__ void swap_trsm(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int c0, int c1,
+                                          LuShared<R>& sm, const int* piv) {
   using T = typename Cx<R>::T;
   constexpr int B = 8;
   const int tid = threadIdx.x;
   for (int e = tid; e < kb * kb; e += kThreads) {
     const int i = e / kb, j = e - i * kb;
-    sm.L11[i * NB + j] = (j < i) ? W[(size_t)(k + i) * ld + k + j] : T{0, 0};
+    sm.buf[i * NB + j] = (j < i) ? W[(size_t)(k + i) * ld + k + j] : T{0, 0};
   }
   __syncthreads();
-  for (int col = k + kb + tid; col < ncols; col += kThreads) {
-    for (int i = 0; i < kb; ++i) {
-      const int r = k + i, p = sm.piv[i];
-      if (p != r) {
-        const T a = W[(size_t)r * ld + col];
-        W[(size_t)r * ld + col] = W[(size_t)p * ld + col];
-        W[(size_t)p * ld + col] = a;
+  for (int col = c0 + tid; col < c1; col += kThreads) {
+    if (piv)
+      for (int i = 0; i < kb; ++i) {
+        const int r = k + i, p = piv[i];
+        if (p != r) {
+          const T a = W[(size_t)r * ld + col];
+          W[(size_t)r * ld + col] = W[(size_t)p * ld + col];
+          W[(size_t)p * ld + col] = a;
+        }
       }
-    }
     for (int b0 = 0; b0 < kb; b0 += B) {
       T u[B];
 #pragma unroll
@@ -354,12 +360,12 @@ __device__ __forceinline__ void swap_trsm(typename Cx<R>::T* __restrict__ W, int
       for (int j = 0; j < b0; ++j) {  // contributions of the solved rows above the block
         const T uj = W[(size_t)(k + j) * ld + col];
 #pragma unroll
-        for (int i = 0; i < B; ++i) u[i] = cfms(u[i], sm.L11[(b0 + i) * NB + j], uj);
+        for (int i = 0; i < B; ++i) u[i] = cfms(u[i], sm.buf[(b0 + i) * NB + j], uj);
       }
 #pragma unroll
       for (int i = 1; i < B; ++i)
 #pragma unroll
-        for (int j = 0; j < i; ++j) u[i] = cfms(u[i], sm.L11[(b0 + i) * NB + b0 + j], u[j]);
+        for (int j = 0; j < i; ++j) u[i] = cfms(u[i], sm.buf[(b0 + i) * NB + b0 + j], u[j]);
 #pragma unroll
       for (int i = 0; i < B; ++i)
         if (b0 + i < kb) W[(size_t)(k + b0 + i) * ld + col] = u[i];
@@ -368,7 +374,97 @@ __device__ __forceinline__ void swap_trsm(typename Cx<R>::T* __restrict__ W, int
   __syncthreads();
 }
 
-// A22 -= L21 U12 on rows [k + kb, N), columns [k + kb, ncols).
+// U = L11^-1 A on rows [k, k + kb) and columns [c0, c1), L11 the unit-lower
+// panel block: its inverse is formed in LDS (row by row, all entries of a row
+// at once) and applied as an MFMA product, each wave taking 16-column tiles
+// (the tile's A rows are in registers before any of them is overwritten).
+template <typename R>
+__device__ __forceinline__ void trsm_inverse(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int c0, int c1,
+                                             LuShared<R>& sm) {
+  using T = typename Cx<R>::T;
+  using MF = Mfma<R>;
+  using acc_t = typename MF::acc_t;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  T* L = sm.buf;             // L11, strictly lower part (zero elsewhere)
+  T* Li = sm.buf + NB * NB;  // its inverse, zero outside [0, kb)^2
+  for (int e = tid; e < NB * NB; e += kThreads) {
+    const int i = e / NB, j = e - i * NB;
+    L[e] = (i < kb && j < i) ? W[(size_t)(k + i) * ld + k + j] : T{0, 0};
+    Li[e] = (i == j && i < kb) ? T{1, 0} : T{0, 0};
+  }
+  __syncthreads();
+  for (int i = 1; i < kb; ++i) {  // Li[i][j] = -sum_{j <= t < i} L[i][t] Li[t][j]
+    if (tid < i) {
+      const int j = tid;
+      T acc{0, 0};
+      for (int t = j; t < i; ++t) acc = cfms(acc, L[i * NB + t], Li[t * NB + j]);
+      Li[i * NB + j] = acc;
+    }
+    __syncthreads();
+  }
+  // A operand: Li rows 16 a + l16, k-columns 4 kq + lk
+  R ar[2][NB / 4], ai[2][NB / 4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int kq = 0; kq < NB / 4; ++kq) {
+      const T v = Li[(16 * a + l16) * NB + 4 * kq + lk];
+      ar[a][kq] = v.x;
+      ai[a][kq] = v.y;
+    }
+  const int ntile = (c1 - c0 + 15) >> 4;
+  for (int tn = wid; tn < ntile; tn += kWaves) {
+    const int col = c0 + 16 * tn + l16;
+    T bq[NB / 4];
+#pragma unroll
+    for (int kq = 0; kq < NB / 4; ++kq) {
+      const int kk = 4 * kq + lk;
+      bq[kq] = (kk < kb && col < c1) ? W[(size_t)(k + kk) * ld + col] : T{0, 0};
+    }
+    acc_t cr[2], ci[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      cr[a] = acc_t{0, 0, 0, 0};
+      ci[a] = acc_t{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int kq = 0; kq < NB / 4; ++kq)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        cr[a] = MF::run(ar[a][kq], bq[kq].x, cr[a]);
+        cr[a] = MF::run(ai[a][kq], -bq[kq].y, cr[a]);
+        ci[a] = MF::run(ar[a][kq], bq[kq].y, ci[a]);
+        ci[a] = MF::run(ai[a][kq], bq[kq].x, ci[a]);
+      }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * a + MF::row(lane, i);
+        if (r < kb && col < c1) W[(size_t)(k + r) * ld + col] = T{cr[a][i], ci[a][i]};
+      }
+  }
+  __syncthreads();
+}
+
+// Interchanges of rows [k, k + kb) with piv[0 .. kb) on columns [c0, c1), in order.
+template <typename T>
+__device__ __forceinline__ void apply_swaps(T* __restrict__ W, int ld, int k, int kb, const int* piv, int c0, int c1) {
+  for (int col = c0 + (int)threadIdx.x; col < c1; col += kThreads)
+    for (int i = 0; i < kb; ++i) {
+      const int r = k + i, p = piv[i];
+      if (p != r) {
+        const T a = W[(size_t)r * ld + col];
+        W[(size_t)r * ld + col] = W[(size_t)p * ld + col];
+        W[(size_t)p * ld + col] = a;
+      }
+    }
+  __syncthreads();
+}
+
+// A22 -= L21 U12 on rows [k + kb, r1), columns [c0, c1), with L21 the panel
+// columns [k, k + kb) and U12 the panel rows.
 // Wave w owns block rows w, w + 4, ... of 32 rows and keeps their (negated)
 // L21 fragments in registers while sweeping the block columns; the four waves
 // sweep the columns in the same order, so a U12 block is fetched from memory
@@ -378,13 +474,13 @@ __device__ __forceinline__ void swap_trsm(typename Cx<R>::T* __restrict__ W, int
 // latency with the other's arithmetic.
 template <typename R>
 __device__ __forceinline__ void trailing_update(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int N,
-                                                int ncols) {
+                                                int c0, int ncols) {
   using T = typename Cx<R>::T;
   using MF = Mfma<R>;
   using acc_t = typename MF::acc_t;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
-  const int r0 = k + kb, c0 = k + kb;
+  const int r0 = k + kb;
   const int mr = N - r0, nc = ncols - c0;
   if (mr <= 0 || nc <= 0) return;
   const int tmn = (mr + 31) >> 5, tnn = (nc + 31) >> 5;
@@ -472,20 +568,247 @@ __device__ __forceinline__ void trailing_update(typename Cx<R>::T* __restrict__ 
   }
 }
 
-// Right-looking blocked LU of columns [0, Ne) of the N x ncols row-major
-// matrix; interchanges touch the panel and the trailing columns only.  When
-// piv_out is given, the pivots are stored there (absolute rows).
-template <typename R, int Q, int SB>
+// A[r0:r1, c0:c1] -= A[r0:r1, k:k+kb] A[k:k+kb, c0:c1] for a block column of
+// width kb <= KB.  The U12 rows are staged in LDS (Us, KB x CS complex) one
+// column slab at a time; each wave owns RT consecutive 16-row tiles of a
+// 64 RT-row group and keeps their (negated) L21 fragments in registers for
+// the whole group, so the trailing block is read and written once per block
+// column and U12 once per row group.
+template <typename R, int KB, int RT>
+__device__ __forceinline__ void wide_update(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int r0, int r1,
+                                            int c0, int c1, typename Cx<R>::T* Us) {
+  using T = typename Cx<R>::T;
+  using MF = Mfma<R>;
+  using acc_t = typename MF::acc_t;
+  constexpr int KQ = KB / 4;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  if (r1 <= r0 || c1 <= c0 || kb <= 0) return;
+  constexpr int GROUP = kWaves * 16 * RT;
+  for (int g0 = r0; g0 < r1; g0 += GROUP) {
+    const int rb = g0 + wid * 16 * RT;
+    R anr[RT][KQ], ani[RT][KQ];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int kq = 0; kq < KQ; ++kq) {
+        const int r = rb + 16 * t + l16, kk = 4 * kq + lk;
+        const T v = (r < r1 && kk < kb) ? W[(size_t)r * ld + k + kk] : T{0, 0};
+        anr[t][kq] = -v.x;
+        ani[t][kq] = -v.y;
+      }
+    for (int s0 = c0; s0 < c1; s0 += CS) {
+      __syncthreads();  // the previous slab is consumed
+      for (int e = tid; e < KB * CS; e += kThreads) {
+        const int i = e / CS, j = e - i * CS;
+        Us[e] = (i < kb && s0 + j < c1) ? W[(size_t)(k + i) * ld + s0 + j] : T{0, 0};
+      }
+      __syncthreads();
+      if (rb < r1) {
+        acc_t cr[RT][2], ci[RT][2];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int r = rb + 16 * t + MF::row(lane, i), col = s0 + 16 * b + l16;
+              const T v = (r < r1 && col < c1) ? W[(size_t)r * ld + col] : T{0, 0};
+              cr[t][b][i] = v.x;
+              ci[t][b][i] = v.y;
+            }
+#pragma unroll
+        for (int kq = 0; kq < KQ; ++kq) {
+          if (4 * kq < kb) {
+            T bq[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bq[b] = Us[(4 * kq + lk) * CS + 16 * b + l16];
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                cr[t][b] = MF::run(anr[t][kq], bq[b].x, cr[t][b]);
+                cr[t][b] = MF::run(ani[t][kq], -bq[b].y, cr[t][b]);
+                ci[t][b] = MF::run(anr[t][kq], bq[b].y, ci[t][b]);
+                ci[t][b] = MF::run(ani[t][kq], bq[b].x, ci[t][b]);
+              }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int r = rb + 16 * t + MF::row(lane, i), col = s0 + 16 * b + l16;
+              if (r < r1 && col < c1) W[(size_t)r * ld + col] = T{cr[t][b][i], ci[t][b][i]};
+            }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Half-precision operands for the 16x16x16 MFMA: lane l holds A[l % 16][4 (l / 16) + j]
+// and B[4 (l / 16) + j][l % 16] for j < 4; the accumulator layout is the FP32 one.
+template <int H>
+struct Half;
+template <>
+struct Half<PXD_HALF_BF16> {
+  typedef short v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ short one(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (short)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (short)(u >> 16);
+  }
+  static __device__ __forceinline__ fx4 run(v4 a, v4 b, fx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Half<PXD_HALF_F16> {
+  typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ _Float16 one(float f) { return (_Float16)f; }
+  static __device__ __forceinline__ fx4 run(v4 a, v4 b, fx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// wide_update for the complex64 factor with L21 and U12 rounded to BF16 or
+// FP16 (the products accumulate in FP32 on top of the FP32 trailing block).
+template <int KB, int RT, int H>
+__device__ __forceinline__ void wide_update_half(float2* __restrict__ W, int ld, int k, int kb, int r0, int r1, int c0,
+                                                 int c1, float2* Us) {
+  using HM = Half<H>;
+  using v4 = typename HM::v4;
+  using MF = Mfma<float>;
+  constexpr int KC = KB / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  if (r1 <= r0 || c1 <= c0 || kb <= 0) return;
+  constexpr int GROUP = kWaves * 16 * RT;
+  for (int g0 = r0; g0 < r1; g0 += GROUP) {
+    const int rb = g0 + wid * 16 * RT;
+    v4 anr[RT][KC], ani[RT][KC];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < KC; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = rb + 16 * t + l16, kk = 16 * c + 4 * lk + j;
+          const float2 v = (r < r1 && kk < kb) ? W[(size_t)r * ld + k + kk] : float2{0, 0};
+          anr[t][c][j] = HM::one(-v.x);
+          ani[t][c][j] = HM::one(-v.y);
+        }
+    for (int s0 = c0; s0 < c1; s0 += CS) {
+      __syncthreads();
+      for (int e = tid; e < KB * CS; e += kThreads) {
+        const int i = e / CS, j = e - i * CS;
+        Us[e] = (i < kb && s0 + j < c1) ? W[(size_t)(k + i) * ld + s0 + j] : float2{0, 0};
+      }
+      __syncthreads();
+      if (rb < r1) {
+        fx4 cr[RT][2], ci[RT][2];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int r = rb + 16 * t + MF::row(lane, i), col = s0 + 16 * b + l16;
+              const float2 v = (r < r1 && col < c1) ? W[(size_t)r * ld + col] : float2{0, 0};
+              cr[t][b][i] = v.x;
+              ci[t][b][i] = v.y;
+            }
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+          if (16 * c < kb) {
+            v4 br[2], bi[2], bin[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const float2 u = Us[(16 * c + 4 * lk + j) * CS + 16 * b + l16];
+                br[b][j] = HM::one(u.x);
+                bi[b][j] = HM::one(u.y);
+                bin[b][j] = HM::one(-u.y);
+              }
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                cr[t][b] = HM::run(anr[t][c], br[b], cr[t][b]);
+                cr[t][b] = HM::run(ani[t][c], bin[b], cr[t][b]);
+                ci[t][b] = HM::run(anr[t][c], bi[b], ci[t][b]);
+                ci[t][b] = HM::run(ani[t][c], br[b], ci[t][b]);
+              }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int r = rb + 16 * t + MF::row(lane, i), col = s0 + 16 * b + l16;
+              if (r < r1 && col < c1) W[(size_t)r * ld + col] = float2{cr[t][b][i], ci[t][b][i]};
+            }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Two-level right-looking LU with partial pivoting of columns [0, Ne) of the
+// N x ncols row-major matrix.  Block columns of KB are factored with 32-wide
+// panels (interchanges applied across the whole block column, so its L is
+// stored in the block's final row order); then the block's interchanges, the
+// solve for its U rows and one rank-KB update reach the columns to its right.
+// Columns left of a block are not permuted by later blocks: solves replay
+// the interchanges block by block.  When piv_out is given the pivots are
+// stored there (absolute rows).
+template <typename R, int Q, int SB, int KB, int RT>
 __device__ __forceinline__ void lu_factor(typename Cx<R>::T* __restrict__ W, int ld, int N, int Ne, int ncols, LuShared<R>& sm,
-                          int* __restrict__ piv_out) {
-  for (int k = 0; k < Ne; k += NB) {
-    const int kb = min(NB, Ne - k);
-    factor_panel<R, Q, SB>(W, ld, N, k, kb, sm);
-    if (piv_out)
-      for (int i = threadIdx.x; i < kb; i += kThreads) piv_out[k + i] = sm.piv[i];
-    swap_trsm<R>(W, ld, k, kb, ncols, sm);
-    trailing_update<R>(W, ld, k, kb, N, ncols);
-    __syncthreads();
+                          int* __restrict__ piv_out, int half = PXD_HALF_NONE) {
+  using T = typename Cx<R>::T;
+  static_assert(KB % NB == 0 && KB <= KBMAX, "block column width");
+  static_assert(sizeof(sm.buf) >= sizeof(T) * KB * CS, "LDS slab must fit the panel buffer");
+  T* Us = sm.buf;  // idle during the wide update
+  for (int K = 0; K < Ne; K += KB) {
+    const int kbb = min(KB, Ne - K), Kend = K + kbb;
+    for (int k = K; k < Kend; k += NB) {
+      const int kb = min(NB, Kend - k);
+      factor_panel<R, Q, SB>(W, ld, N, k, kb, sm);
+      for (int i = threadIdx.x; i < kb; i += kThreads) {
+        sm.bpiv[k - K + i] = sm.piv[i];
+        if (piv_out) piv_out[k + i] = sm.piv[i];
+      }
+      apply_swaps<T>(W, ld, k, kb, sm.piv, K, k);        // block columns left of the panel
+      swap_trsm<R>(W, ld, k, kb, k + kb, Kend, sm, sm.piv);  // and right of it, inside the block
+      trailing_update<R>(W, ld, k, kb, N, k + kb, Kend);
+      __syncthreads();
+    }
+    if (Kend < ncols) {
+      apply_swaps<T>(W, ld, K, kbb, sm.bpiv, Kend, ncols);
+      for (int k = K; k < Kend; k += NB) {  // U rows of the block: L11^-1 A12, 32 rows at a time
+        const int kb = min(NB, Kend - k);
+        trsm_inverse<R>(W, ld, k, kb, Kend, ncols, sm);
+        trailing_update<R>(W, ld, k, kb, Kend, Kend, ncols);
+        __syncthreads();
+      }
+      if constexpr (sizeof(R) == 4) {
+        if (half == PXD_HALF_BF16)
+          wide_update_half<KB, RT, PXD_HALF_BF16>(W, ld, K, kbb, Kend, N, Kend, ncols, Us);
+        else if (half == PXD_HALF_F16)
+          wide_update_half<KB, RT, PXD_HALF_F16>(W, ld, K, kbb, Kend, N, Kend, ncols, Us);
+        else
+          wide_update<R, KB, RT>(W, ld, K, kbb, Kend, N, Kend, ncols, Us);
+      } else {
+        wide_update<R, KB, RT>(W, ld, K, kbb, Kend, N, Kend, ncols, Us);
+      }
+    }
   }
 }
 
@@ -592,7 +915,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_plain(EvalParams p) {
     if (tid == 0) sm.bad = 0;
     __syncthreads();
     gather_item<T, double2>(W, ld, p.Z128 + (size_t)f * p.M * p.M, p.M, sI, N, p.P, p.port_len, p.z0, true);
-    lu_factor<double, Q, SB>(W, ld, N, N - p.P, N + p.P, sm, nullptr);
+    lu_factor<double, Q, SB, KB_PLAIN, 1>(W, ld, N, N - p.P, N + p.P, sm, nullptr);
     int st = port_solve_and_s(W, ld, N, p.P, p.port_len, p.z0, Sout);
     if (tid == 0) {
       if (sm.bad && st == PXD_STATUS_OK) st = PXD_STATUS_SINGULAR;
@@ -644,17 +967,18 @@ __device__ __forceinline__ void rows_update(const float2* __restrict__ row, int 
 
 // Solve (L U) x = P b in complex64 for the P right-hand sides held in LDS
 // (b[row * P + j]), using the factor in W (unit-lower L below the diagonal,
-// U on and above) and the per-panel pivots.  Interchanges were applied only
-// to the panel and trailing columns during the factorisation, so they are
-// replayed panel by panel between the block updates.
+// U on and above) and the pivots.  Interchanges were applied only to a block
+// column and the columns right of it during the factorisation, so they are
+// replayed block column by block column between the eliminations.
 __device__ __forceinline__ void lu_solve_c64(const float2* __restrict__ W, int ld, int N, const int* __restrict__ piv,
                                              float2* b, int P) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  // forward: b <- L^-1 P b
+  // forward: b <- L^-1 P b; a block column's interchanges all precede its
+  // eliminations (its L is stored in the block's final row order)
   for (int k = 0; k < N; k += NB) {
     const int kb = min(NB, N - k);
-    if (tid < P)
-      for (int i = 0; i < kb; ++i) {
+    if (tid < P && k % KB_MIXED == 0)
+      for (int i = 0; i < min(KB_MIXED, N - k); ++i) {
         const int r = k + i, q = piv[r];
         if (q != r) {
           const float2 t = b[r * P + tid];
@@ -786,15 +1110,23 @@ __device__ __forceinline__ void residual_fp64(const double2* __restrict__ Zf, in
   __syncthreads();
 }
 
+// Absolute floor of the refinement target on S, above what FP64 residuals of
+// these systems resolve (~kappa x 1e-16 with kappa up to ~1e5).
+constexpr double kIrAbsFloor = 1e-11;
+
 // Mixed precision item: complex64 LU of Z_A, initial complex64 solve, then
-// refinement with FP64 residuals until the correction of every port current,
-// expressed as the change it makes to S_ij = delta_ij - 2 Z0 l_i x_ij, is at
-// most ir_tol.  Items that do not converge are queued for the FP64 path.
+// refinement with FP64 residuals.  After each step the error left in every
+// S_ij = delta_ij - 2 Z0 l_i x_ij is bounded by rho / (1 - rho) times the
+// largest change the step made to any S entry, rho being the contraction, the
+// ratio of the last two largest changes (so at least two steps are taken).
+// Refinement stops when that estimate is below ir_tol |S_ij| + kIrAbsFloor
+// for every entry.  Items that do not converge are queued for the FP64 path.
 template <int Q, int SB>
 __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
   using T = float2;
   __shared__ LuShared<float> sm;
   __shared__ int s_item, s_conv;
+  __shared__ double s_ds[16], s_sabs[16], s_mprev;
   extern __shared__ char dyn[];
   int* sI = reinterpret_cast<int*>(dyn);
   float2* b = reinterpret_cast<float2*>(dyn + ((size_t)p.nmax * 4 + 15) / 16 * 16);
@@ -825,7 +1157,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
     __syncthreads();
     const double2* Zf128 = p.Z128 + (size_t)f * p.M * p.M;
     gather_item<T, float2>(W, ld, p.Z64 + (size_t)f * p.M * p.M, p.M, sI, N, P, p.port_len, p.z0, false);
-    lu_factor<float, Q, SB>(W, ld, N, N, N, sm, piv);
+    lu_factor<float, Q, SB, KB_MIXED, 2>(W, ld, N, N, N, sm, piv, p.half);
     // x0 = (LU)^-1 V
     for (int e = tid; e < N * P; e += kThreads) {
       const int i = e / P, jr = e - i * P;
@@ -837,22 +1169,37 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
     __syncthreads();
     int iters = 0;
     bool conv = false;
+    if (tid == 0) s_mprev = 0.0;
     while (iters < p.ir_max) {
       residual_fp64(Zf128, p.M, sI, N, P, p.port_len, p.z0, x, b);
       lu_solve_c64(W, ld, N, piv, b, P);
-      if (tid == 0) s_conv = 1;
-      __syncthreads();
       for (int e = tid; e < N * P; e += kThreads) {
         const double2 d = double2{(double)b[e].x, (double)b[e].y};
         double2 xv = x[e];
         xv.x += d.x;
         xv.y += d.y;
         x[e] = xv;
-        if (e >= (N - P) * P) {  // port rows decide convergence: the change of S_ij (Eq. 6) this step made
-          const int pi = e / P - (N - P);
-          const double ds = 2.0 * p.z0 * p.port_len[pi] * sqrt(d.x * d.x + d.y * d.y);
-          if (!(ds <= p.ir_tol)) s_conv = 0;
+        if (e >= (N - P) * P) {  // port rows: the change of S_ij (Eq. 6) this step made, and S_ij itself
+          const int pi = e / P - (N - P), jr = e - (e / P) * P;
+          const double g = 2.0 * p.z0 * p.port_len[pi];
+          s_ds[pi * P + jr] = g * sqrt(d.x * d.x + d.y * d.y);
+          const double sr = (pi == jr ? 1.0 : 0.0) - g * xv.x, si = -g * xv.y;
+          s_sabs[pi * P + jr] = sqrt(sr * sr + si * si);
         }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        // error left after this correction ~ rho / (1 - rho) of it, rho the observed contraction
+        double m = 0.0;
+        for (int q = 0; q < P * P; ++q) m = (s_ds[q] > m || s_ds[q] != s_ds[q]) ? s_ds[q] : m;
+        const double rho = (iters == 0) ? 1.0 : (s_mprev > 0.0 ? m / s_mprev : 0.0);
+        // the contraction acts on the whole error, so what is left in any
+        // entry is bounded by rho times the largest change, not its own change
+        const double left = m * rho / (1.0 - rho);
+        bool ok = rho < 0.9;
+        for (int q = 0; q < P * P && ok; ++q) ok = left <= p.ir_tol * s_sabs[q] + kIrAbsFloor;
+        s_conv = ok ? 1 : 0;
+        s_mprev = m;
       }
       __syncthreads();
       ++iters;

@@ -37,7 +37,13 @@ struct EvalParams {
   int ir_max;
   double ir_tol;
   int schedule;         // PXD_SCHED_FREQ_MAJOR or PXD_SCHED_SIZE_MAJOR (implicit order only)
+  int half;             // mixed: operands of the rank-KB trailing updates (PXD_HALF_*)
 };
+
+// Operand precision of the complex64 factor's block-column updates.
+#define PXD_HALF_NONE 0
+#define PXD_HALF_BF16 1
+#define PXD_HALF_F16 2
 
 // Per-slot layout of the workspace (byte offsets).
 struct SlotLayout {

@@ -35,7 +35,7 @@ def oracle_maps(st, Z, maps, freqs):
 
 def check(S, F, S_o, F_o, prec):
     assert np.abs(S - S_o).max() <= S_TOL[prec], np.abs(S - S_o).max()
-    assert np.all(np.abs(F - F_o) <= FOM_RTOL * F_o)
+    assert np.all(np.abs(F - F_o) <= FOM_RTOL * F_o), np.max(np.abs(F - F_o) / F_o)
 
 
 @pytest.mark.parametrize("prec", [pxd.PREC_FP64, pxd.PREC_MIXED32])
