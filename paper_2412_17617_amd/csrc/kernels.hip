@@ -17,7 +17,8 @@
 // and no storage of L or U is needed for the FP64 path.
 //
 // Panel factorisation: panels of NB = 32 columns, factored in sub-blocks of
-// SB columns held in registers (Q rows per thread, N <= 256 Q, Q SB <= 16); the pivot
+// SB columns held in registers (Q rows per thread, N <= 256 Q, Q SB <= 16 for
+// complex128 and <= 32 for complex64); the pivot
 // search is a wave shuffle reduction plus one LDS exchange per column.  Row
 // interchanges are applied to the trailing columns lazily, fused with the
 // triangular solve of the U block.  The trailing update A22 -= L21 U12 is a
@@ -1110,6 +1111,57 @@ __device__ __forceinline__ void residual_fp64(const double2* __restrict__ Zf, in
   __syncthreads();
 }
 
+// Port-current corrections from a residual without a solve.  Z_A is
+// symmetric, so row p_i of Z_A^-1 is x_i^T / l_i (x_i the solution for port
+// i's excitation l_i e_{p_i}); the correction of x[p_i][j] is therefore
+// x_i^T r_j / l_i, exact up to a term second order in the solution error
+// (dual-weighted residual).  x is the current solution (FP64), r = b the
+// residual rounded to complex64.  delta[i P + j] receives the corrections.
+__device__ __forceinline__ void port_corrections(const double2* __restrict__ x, const float2* b, int N, int P,
+                                                 const double* __restrict__ plen, double2* delta, double2* part) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double2 acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = double2{0.0, 0.0};
+  for (int n = tid; n < N; n += kThreads) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < P) {
+        const double2 xi = x[(size_t)n * P + i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < P) {
+            const float2 rj = b[n * P + j];
+            acc[i * 4 + j].x += xi.x * rj.x - xi.y * rj.y;
+            acc[i * 4 + j].y += xi.x * rj.y + xi.y * rj.x;
+          }
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if ((q >> 2) < P && (q & 3) < P) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        acc[q].x += __shfl_xor(acc[q].x, off, 64);
+        acc[q].y += __shfl_xor(acc[q].y, off, 64);
+      }
+    }
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) part[wid * 16 + q] = acc[q];
+  __syncthreads();
+  if (tid < P * P) {
+    const int i = tid / P, j = tid - i * P;
+    double2 sum = double2{0.0, 0.0};
+    for (int w = 0; w < kWaves; ++w) {
+      sum.x += part[w * 16 + i * 4 + j].x;
+      sum.y += part[w * 16 + i * 4 + j].y;
+    }
+    delta[tid] = double2{sum.x / plen[i], sum.y / plen[i]};
+  }
+  __syncthreads();
+}
+
 // Absolute floor of the refinement target on S, above what FP64 residuals of
 // these systems resolve (~kappa x 1e-16 with kappa up to ~1e5).
 constexpr double kIrAbsFloor = 1e-11;
@@ -1119,14 +1171,18 @@ constexpr double kIrAbsFloor = 1e-11;
 // S_ij = delta_ij - 2 Z0 l_i x_ij is bounded by rho / (1 - rho) times the
 // largest change the step made to any S entry, rho being the contraction, the
 // ratio of the last two largest changes (so at least two steps are taken).
-// Refinement stops when that estimate is below ir_tol |S_ij| + kIrAbsFloor
-// for every entry.  Items that do not converge are queued for the FP64 path.
+// Each step first forms the FP64 residual and the port corrections it implies
+// (port_corrections, no solve); when the stop test passes on those, they are
+// applied and the step ends there, otherwise the full correction is solved.
+// The stop test: the estimate is below ir_tol |S_ij| + kIrAbsFloor for every
+// entry.  Items that do not converge are queued for the FP64 path.
 template <int Q, int SB>
 __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
   using T = float2;
   __shared__ LuShared<float> sm;
   __shared__ int s_item, s_conv;
   __shared__ double s_ds[16], s_sabs[16], s_mprev;
+  __shared__ double2 s_delta[16], s_part[kWaves * 16];
   extern __shared__ char dyn[];
   int* sI = reinterpret_cast<int*>(dyn);
   float2* b = reinterpret_cast<float2*>(dyn + ((size_t)p.nmax * 4 + 15) / 16 * 16);
@@ -1172,6 +1228,39 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
     if (tid == 0) s_mprev = 0.0;
     while (iters < p.ir_max) {
       residual_fp64(Zf128, p.M, sI, N, P, p.port_len, p.z0, x, b);
+      ++iters;
+      // what this step would change at the ports, without solving
+      port_corrections(x, b, N, P, p.port_len, s_delta, s_part);
+      if (tid == 0) {
+        double m = 0.0;
+        for (int q = 0; q < P * P; ++q) {
+          const int i = q / P, j = q - i * P;
+          const double g = 2.0 * p.z0 * p.port_len[i];
+          const double ds = g * sqrt(s_delta[q].x * s_delta[q].x + s_delta[q].y * s_delta[q].y);
+          m = (ds > m || ds != ds) ? ds : m;
+          const double2 xv = x[(size_t)(N - P + i) * P + j];
+          const double sr = (i == j ? 1.0 : 0.0) - g * (xv.x + s_delta[q].x), si = -g * (xv.y + s_delta[q].y);
+          s_sabs[q] = sqrt(sr * sr + si * si);
+        }
+        // the contraction acts on the whole error, so what is left in any
+        // entry is bounded by rho times the largest change, not its own change
+        const double rho = (iters == 1) ? 1.0 : (s_mprev > 0.0 ? m / s_mprev : 0.0);
+        const double left = m * rho / (1.0 - rho);
+        bool ok = rho < 0.9;
+        for (int q = 0; q < P * P && ok; ++q) ok = left <= p.ir_tol * s_sabs[q] + kIrAbsFloor;
+        s_conv = ok ? 1 : 0;
+      }
+      __syncthreads();
+      conv = s_conv != 0;
+      if (conv) {  // converged: the port corrections finish the step
+        if (tid < P * P) {
+          double2* xv = x + (size_t)(N - P + tid / P) * P + tid % P;
+          xv->x += s_delta[tid].x;
+          xv->y += s_delta[tid].y;
+        }
+        __syncthreads();
+        break;
+      }
       lu_solve_c64(W, ld, N, piv, b, P);
       for (int e = tid; e < N * P; e += kThreads) {
         const double2 d = double2{(double)b[e].x, (double)b[e].y};
@@ -1179,33 +1268,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
         xv.x += d.x;
         xv.y += d.y;
         x[e] = xv;
-        if (e >= (N - P) * P) {  // port rows: the change of S_ij (Eq. 6) this step made, and S_ij itself
+        if (e >= (N - P) * P) {  // port rows: the change of S_ij (Eq. 6) this step made
           const int pi = e / P - (N - P), jr = e - (e / P) * P;
-          const double g = 2.0 * p.z0 * p.port_len[pi];
-          s_ds[pi * P + jr] = g * sqrt(d.x * d.x + d.y * d.y);
-          const double sr = (pi == jr ? 1.0 : 0.0) - g * xv.x, si = -g * xv.y;
-          s_sabs[pi * P + jr] = sqrt(sr * sr + si * si);
+          s_ds[pi * P + jr] = 2.0 * p.z0 * p.port_len[pi] * sqrt(d.x * d.x + d.y * d.y);
         }
       }
       __syncthreads();
       if (tid == 0) {
-        // error left after this correction ~ rho / (1 - rho) of it, rho the observed contraction
         double m = 0.0;
         for (int q = 0; q < P * P; ++q) m = (s_ds[q] > m || s_ds[q] != s_ds[q]) ? s_ds[q] : m;
-        const double rho = (iters == 0) ? 1.0 : (s_mprev > 0.0 ? m / s_mprev : 0.0);
-        // the contraction acts on the whole error, so what is left in any
-        // entry is bounded by rho times the largest change, not its own change
-        const double left = m * rho / (1.0 - rho);
-        bool ok = rho < 0.9;
-        for (int q = 0; q < P * P && ok; ++q) ok = left <= p.ir_tol * s_sabs[q] + kIrAbsFloor;
-        s_conv = ok ? 1 : 0;
         s_mprev = m;
       }
       __syncthreads();
-      ++iters;
-      conv = s_conv != 0;
-      __syncthreads();
-      if (conv) break;
     }
     if (tid == 0) {
       atomicAdd(p.ir_iters, iters);
@@ -1340,25 +1414,29 @@ static hipError_t launch_mixed_variant(hipStream_t s, const EvalParams& p, int g
   return hipGetLastError();
 }
 
+// The complex64 kernel holds twice as many sub-panel columns in the same registers.
+template <int Q>
+constexpr int msb_of(int half) { return half ? 16 / Q : 32 / Q; }
+
 // Raise the dynamic LDS limit of the mixed kernel variant the launch will use
 // (host-side attribute; called outside any stream capture).
 hipError_t prepare_eval_mixed(const EvalParams& p, int half_sb) {
   const int Q = rows_per_thread(p.nmax);
   const size_t lds = eval_mixed_lds(p.nmax, p.P);
-  if (Q <= 1) return half_sb ? prepare_mixed_variant<1, sb_of<1>(1)>(lds) : prepare_mixed_variant<1, sb_of<1>(0)>(lds);
-  if (Q <= 2) return half_sb ? prepare_mixed_variant<2, sb_of<2>(1)>(lds) : prepare_mixed_variant<2, sb_of<2>(0)>(lds);
-  if (Q <= 4) return half_sb ? prepare_mixed_variant<4, sb_of<4>(1)>(lds) : prepare_mixed_variant<4, sb_of<4>(0)>(lds);
-  if (Q <= 8) return half_sb ? prepare_mixed_variant<8, sb_of<8>(1)>(lds) : prepare_mixed_variant<8, sb_of<8>(0)>(lds);
+  if (Q <= 1) return half_sb ? prepare_mixed_variant<1, msb_of<1>(1)>(lds) : prepare_mixed_variant<1, msb_of<1>(0)>(lds);
+  if (Q <= 2) return half_sb ? prepare_mixed_variant<2, msb_of<2>(1)>(lds) : prepare_mixed_variant<2, msb_of<2>(0)>(lds);
+  if (Q <= 4) return half_sb ? prepare_mixed_variant<4, msb_of<4>(1)>(lds) : prepare_mixed_variant<4, msb_of<4>(0)>(lds);
+  if (Q <= 8) return half_sb ? prepare_mixed_variant<8, msb_of<8>(1)>(lds) : prepare_mixed_variant<8, msb_of<8>(0)>(lds);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_eval_mixed(hipStream_t s, const EvalParams& p, int grid, int half_sb) {
   const int Q = rows_per_thread(p.nmax);
   const size_t lds = eval_mixed_lds(p.nmax, p.P);
-  if (Q <= 1) return half_sb ? launch_mixed_variant<1, sb_of<1>(1)>(s, p, grid, lds) : launch_mixed_variant<1, sb_of<1>(0)>(s, p, grid, lds);
-  if (Q <= 2) return half_sb ? launch_mixed_variant<2, sb_of<2>(1)>(s, p, grid, lds) : launch_mixed_variant<2, sb_of<2>(0)>(s, p, grid, lds);
-  if (Q <= 4) return half_sb ? launch_mixed_variant<4, sb_of<4>(1)>(s, p, grid, lds) : launch_mixed_variant<4, sb_of<4>(0)>(s, p, grid, lds);
-  if (Q <= 8) return half_sb ? launch_mixed_variant<8, sb_of<8>(1)>(s, p, grid, lds) : launch_mixed_variant<8, sb_of<8>(0)>(s, p, grid, lds);
+  if (Q <= 1) return half_sb ? launch_mixed_variant<1, msb_of<1>(1)>(s, p, grid, lds) : launch_mixed_variant<1, msb_of<1>(0)>(s, p, grid, lds);
+  if (Q <= 2) return half_sb ? launch_mixed_variant<2, msb_of<2>(1)>(s, p, grid, lds) : launch_mixed_variant<2, msb_of<2>(0)>(s, p, grid, lds);
+  if (Q <= 4) return half_sb ? launch_mixed_variant<4, msb_of<4>(1)>(s, p, grid, lds) : launch_mixed_variant<4, msb_of<4>(0)>(s, p, grid, lds);
+  if (Q <= 8) return half_sb ? launch_mixed_variant<8, msb_of<8>(1)>(s, p, grid, lds) : launch_mixed_variant<8, msb_of<8>(0)>(s, p, grid, lds);
   return hipErrorInvalidValue;
 }
 
