@@ -1,0 +1,136 @@
+"""Depth-increasing all-way tree navigation (Algorithm 1) on the GPU evaluator.
+
+The search state is a multi-state pixel map: the pixel at in-plane position j
+stacked over the L layers takes one of 2^L states (bit l = metal on layer l,
+Section II-D, Fig. 4).  One iteration builds the tree of depth D below the
+current map: D distinct pixels (taken in turn from a caller-given order), and
+for each level every other state of that level's pixel applied to every node
+of the level above.  All nodes of all levels are candidate maps differing from
+the root in at most D pixels, so the whole tree is one flip batch and one
+persistent launch of the evaluator.  The best leaf of the deepest level is
+accepted only if it improves strictly; M(D) failures raise D, and saturation
+at the deepest depth restarts from a random map (caller-given).
+
+Readings where the algorithm is silent: all nodes of one depth expand the same
+pixel; the restart happens when the count saturates at the deepest depth; the
+evaluation budget counts every candidate evaluated.  Optionally a surrogate
+(``Surrogate``) ranks the deepest level and only its best k leaves are solved;
+the exact evaluator still judges every accepted change.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class SearchResult:
+    best_fom: float
+    best_map: np.ndarray
+    evaluations: int
+    trace: list = field(default_factory=list)  # (evaluations, current FoM) after each tree
+    restarts: int = 0
+    accepted: int = 0
+
+
+class TreeSearch:
+    def __init__(self, evaluator, n_layers: int, n_pix: int, d_init: int = 1, d_max: int = 2, m_of_depth=(10, 3)):
+        if not (1 <= d_init <= d_max) or len(m_of_depth) < d_max:
+            raise ValueError("need 1 <= d_init <= d_max and one M(D) per depth")
+        self.ev = evaluator
+        self.L, self.n_pix = n_layers, n_pix
+        self.d_init, self.d_max, self.m = d_init, d_max, tuple(m_of_depth)
+
+    def _tree(self, P, path):
+        """Flip lists (CSR, relative to P) of every node below P, level by
+        level, and the slice of the deepest level."""
+        L, n = self.L, self.n_pix
+        Pl = P.reshape(L, n)
+        nodes = [np.zeros(0, np.int32)]  # cells toggled relative to P
+        offs, cells, start = [0], [], 0
+        for j in path:
+            s = int(sum(int(Pl[l, j]) << l for l in range(L)))
+            nxt = []
+            for flips in nodes:
+                for t in range(1 << L):
+                    if t == s:
+                        continue
+                    diff = s ^ t
+                    cj = np.array([l * n + j for l in range(L) if (diff >> l) & 1], np.int32)
+                    nxt.append(np.concatenate([flips, cj]))
+            start = len(offs) - 1
+            for f in nxt:
+                cells.append(f)
+                offs.append(offs[-1] + len(f))
+            nodes = nxt
+        cells = np.concatenate(cells).astype(np.int32) if cells else np.zeros(0, np.int32)
+        return np.asarray(offs, np.int32), cells, start, len(offs) - 1
+
+    def _fom(self, m):
+        _, F, _, _ = self.ev.evaluate_flips(m, np.array([0, 0], np.int32), np.zeros(0, np.int32), want_S=False)
+        return float(F[0])
+
+    def run(self, start_map, pixel_order, restart_maps, max_evals: int, prefilter=None) -> SearchResult:
+        """prefilter: None, or (surrogate, k, rank) where rank(surrogate, P,
+        offsets, cells) returns the surrogate's predicted FoM of each
+        candidate; then only the best k of the deepest level are solved."""
+        P = np.array(start_map, np.uint8)
+        F = self._fom(P)
+        res = SearchResult(F, P.copy(), 1)
+        D, count, cursor = self.d_init, 0, 0
+        order = np.asarray(pixel_order)
+        while res.evaluations < max_evals:
+            path = []
+            while len(path) < D:
+                j = int(order[cursor % len(order)])
+                cursor += 1
+                if j not in path:
+                    path.append(j)
+            offs, cells, lo, hi = self._tree(P, path)
+            if prefilter is None:
+                _, Fc, st, _ = self.ev.evaluate_flips(P, offs, cells, want_S=False)
+                res.evaluations += len(offs) - 1
+                leaves = np.arange(lo, hi)
+                Fl = Fc[lo:hi]
+            else:
+                sur, k, rank = prefilter
+                upper = offs[:lo + 1]  # the levels above the leaves are solved exactly
+                if lo > 0:
+                    self.ev.evaluate_flips(P, upper, cells[:upper[-1]], want_S=False)
+                    res.evaluations += lo
+                pred = rank(sur, P, offs, cells)[lo:hi]
+                pick = np.argsort(pred, kind="stable")[:k] + lo
+                sub = np.zeros(len(pick) + 1, np.int32)
+                sub[1:] = np.cumsum([offs[i + 1] - offs[i] for i in pick])
+                sc = np.concatenate([cells[offs[i]:offs[i + 1]] for i in pick]).astype(np.int32)
+                _, Fl, st, _ = self.ev.evaluate_flips(P, sub, sc, want_S=False)
+                res.evaluations += len(pick)
+                leaves = pick
+            k = int(np.argmin(Fl))  # lowest index among equal minima
+            if Fl[k] < F:
+                leaf = leaves[k]
+                P = P.copy()
+                P[cells[offs[leaf]:offs[leaf + 1]]] ^= 1
+                F = float(Fl[k])
+                count = 0
+                res.accepted += 1
+                if F < res.best_fom:
+                    res.best_fom, res.best_map = F, P.copy()
+            else:
+                count += 1
+                if count >= self.m[D - 1]:
+                    count = 0
+                    if D >= self.d_max:
+                        P = np.array(next(restart_maps), np.uint8)
+                        F = self._fom(P)
+                        res.evaluations += 1
+                        res.restarts += 1
+                        if F < res.best_fom:
+                            res.best_fom, res.best_map = F, P.copy()
+                        D = self.d_init
+                    else:
+                        D += 1
+            res.trace.append((res.evaluations, F))
+        return res

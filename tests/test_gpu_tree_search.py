@@ -1,0 +1,71 @@
+"""Algorithm 1 on the GPU evaluator against the oracle's reference search
+(GPU): same seeded pixel order and restart maps, same decisions."""
+
+import numpy as np
+import pytest
+
+from oracle import search
+from paper_2412_17617_amd import pxd
+from paper_2412_17617_amd.tree_search import TreeSearch
+from synth import bernoulli_map, get_spec, permutation
+
+from gpu_common import make_evaluator, oracle_parent
+
+pytestmark = pytest.mark.gpu
+
+
+def restart_maps(n_cells, seed):
+    k = 0
+    while True:
+        yield bernoulli_map(n_cells, 0.5, seed * 1000 + k)
+        k += 1
+
+
+def test_tree_search_follows_the_reference():
+    spec = get_spec("tiny4x2")  # two layers: 4-state pixels, 3-way branching
+    st, Z, freqs = oracle_parent(spec)
+    n_pix = spec.nx * spec.ny
+    order = permutation(n_pix, 5)
+    start = bernoulli_map(spec.n_cells, 0.5, 6)
+    kw = dict(d_init=1, d_max=2, m_of_depth=(4, 2))
+    ref = search.tree_search(lambda m: search.evaluate_gather(st, Z, m, freqs)[1], start, spec.n_layers, n_pix,
+                             order, restart_maps(spec.n_cells, 7), 400, **kw)
+    ev, _ = make_evaluator(spec, Z, freqs)
+    res = TreeSearch(ev, spec.n_layers, n_pix, **kw).run(start, order, restart_maps(spec.n_cells, 7), 400)
+    ev.close()
+    best_F, best_P, evals, trace, nres = ref
+    print(f"reference best {best_F:.6g} after {evals} evaluations, {nres} restarts; "
+          f"GPU best {res.best_fom:.6g} after {res.evaluations}, {res.restarts} restarts, {res.accepted} accepted")
+    assert res.evaluations == evals and res.restarts == nres
+    assert len(res.trace) == len(trace)
+    for (e1, f1), (e2, f2) in zip(res.trace, trace):
+        assert e1 == e2 and abs(f1 - f2) <= 1e-6 * f2
+    assert np.array_equal(res.best_map, best_P)
+    assert abs(res.best_fom - best_F) <= 1e-6 * best_F
+
+
+def test_prefiltered_tree_search_is_judged_exactly():
+    """Depth-two trees with the deepest level ranked by a surrogate and only
+    its best 4 leaves solved: every accepted FoM is an exact solve."""
+    torch = pytest.importorskip("torch")
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec)
+    n_pix = spec.nx * spec.ny
+    ev, _ = make_evaluator(spec, Z, freqs)
+    sur = pxd.Surrogate(spec.n_layers, spec.ny, spec.nx, freqs, freqs[0], freqs[-1], entries=((0, 0), (1, 0), (2, 0)),
+                        hidden=32, channels=(8, 8, 16, 16), max_batch=64)
+
+    def rank(s, P, offs, cells):
+        fp = torch.zeros(len(offs) - 1, dtype=torch.float64, device="cuda:0")
+        s.rank(ev, torch.from_numpy(P).to("cuda:0"), torch.from_numpy(offs).to("cuda:0"),
+               torch.from_numpy(cells).to("cuda:0"), 0, fp, None)
+        return fp.cpu().numpy()
+
+    res = TreeSearch(ev, spec.n_layers, n_pix, d_init=2, d_max=2, m_of_depth=(1, 3)).run(
+        bernoulli_map(spec.n_cells, 0.5, 8), permutation(n_pix, 9), restart_maps(spec.n_cells, 10), 150,
+        prefilter=(sur, 4, rank))
+    exact = search.evaluate_gather(st, Z, res.best_map, freqs)[1]
+    assert abs(res.best_fom - exact) <= 1e-6 * exact
+    assert res.accepted >= 1
+    sur.close()
+    ev.close()
