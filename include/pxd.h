@@ -167,6 +167,12 @@ int pxd_set_fom(pxd_ctx* ctx, int32_t n_terms, const pxd_fom_term* terms, const 
  * terms whose S entry exceeds the port count are dropped. */
 int pxd_set_fom_paper(pxd_ctx* ctx);
 
+/* FoM variants of Section III-D, as alternative term tables (bands as above). */
+#define PXD_FOM_PAPER 0 /* Eqs. 8-9 */
+#define PXD_FOM_REJ 1   /* rw_s1, rw_s2 replaced by 10^((-S_dB - 45) / 10) */
+#define PXD_FOM_ISO 2   /* Eqs. 8-9 plus 1/rw_oi^iso = 1 / 10^((-S32_dB - 35) / 15) over p1 and p2 */
+int pxd_set_fom_variant(pxd_ctx* ctx, int32_t variant);
+
 /* Evaluate candidates given as flips of a base map: candidate c toggles cells
  * cells[offsets[c] .. offsets[c+1]).  Outputs (host, caller-owned, any may be
  * NULL): S_out n_cand x F x P x P complex128; fom_out n_cand; status n_cand

@@ -65,19 +65,32 @@ def rewards(S_f: np.ndarray) -> dict:
         "oi": ten(None if s32 is None else (-s32 - 20.0) / 15.0),
         "m1": ten((-15.0 - s11) / 10.0),
         "m2": ten((-15.0 - s11) / 10.0),
+        # Section III-D variants: stricter rejection terms, and an isolation term
+        "s1rej": ten(None if s21 is None else (-s21 - 45.0) / 10.0),
+        "s2rej": ten(None if s31 is None else (-s31 - 45.0) / 10.0),
+        "oiiso": ten(None if s32 is None else (-s32 - 35.0) / 15.0),
     }
 
 
 BAND_TERMS = (("p1", ("p1", "m1", "s2")), ("p2", ("p2", "m2", "s1")), ("i", ("oi",)), ("s", ("s3", "s4")))
 
+# Section III-D: "rej" replaces rw_s1 and rw_s2 by their stricter forms; "iso"
+# adds the isolation term in both passbands.
+VARIANT_TERMS = {
+    "paper": BAND_TERMS,
+    "rej": (("p1", ("p1", "m1", "s2rej")), ("p2", ("p2", "m2", "s1rej")), ("i", ("oi",)), ("s", ("s3", "s4"))),
+    "iso": (("p1", ("p1", "m1", "s2", "oiiso")), ("p2", ("p2", "m2", "s1", "oiiso")), ("i", ("oi",)),
+            ("s", ("s3", "s4"))),
+}
 
-def fom(S: np.ndarray, freqs) -> float:
-    """Eq. 8 for one candidate: S is (F, P, P)."""
+
+def fom(S: np.ndarray, freqs, variant: str = "paper") -> float:
+    """Eq. 8 for one candidate: S is (F, P, P); variant picks the term table."""
     masks = dict(zip(("p1", "p2", "i", "s"), band_sets(freqs)))
     total = 0.0
     for f_idx in range(len(freqs)):
         rw = rewards(S[f_idx])
-        for band, terms in BAND_TERMS:
+        for band, terms in VARIANT_TERMS[variant]:
             if masks[band][f_idx]:
                 for t in terms:
                     if rw[t] is not None:

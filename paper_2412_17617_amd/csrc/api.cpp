@@ -421,8 +421,11 @@ int pxd_set_fom(pxd_ctx* ctx, int32_t n_terms, const pxd_fom_term* terms, const 
   return PXD_OK;
 }
 
-int pxd_set_fom_paper(pxd_ctx* ctx) {
+int pxd_set_fom_paper(pxd_ctx* ctx) { return pxd_set_fom_variant(ctx, PXD_FOM_PAPER); }
+
+int pxd_set_fom_variant(pxd_ctx* ctx, int32_t variant) {
   if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  if (variant < PXD_FOM_PAPER || variant > PXD_FOM_ISO) return ctx->fail(PXD_EINVAL, "unknown FoM variant");
   if (!ctx->Z128.p || !ctx->cell_a.p) return ctx->fail(PXD_ENOTLOADED, "load the parent and the map first");
   // Section III-B bands: 0 = channel 1, 1 = channel 2, 2 = between, 3 = rest of 3-9 GHz
   std::vector<int8_t> band(ctx->F);
@@ -451,8 +454,16 @@ int pxd_set_fom_paper(pxd_ctx* ctx) {
       {3, 1, 0, 20.0 / 18.0, 20.0 / 18.0},  // 1/rw_s3 on S21
       {3, 2, 0, 20.0 / 18.0, 20.0 / 18.0},  // 1/rw_s4 on S31
   };
+  std::vector<Row> table(std::begin(rows), std::end(rows));
+  if (variant == PXD_FOM_REJ) {  // Section III-D: rw_s1, rw_s2 at -45 dB with a /10 slope
+    for (Row& r : table)
+      if ((r.band == 0 && r.i == 2 && r.j == 0) || (r.band == 1 && r.i == 1 && r.j == 0)) r.c = 4.5, r.e = 2.0;
+  } else if (variant == PXD_FOM_ISO) {  // Section III-D: isolation term in both passbands
+    table.push_back(Row{0, 2, 1, 35.0 / 15.0, 20.0 / 15.0});
+    table.push_back(Row{1, 2, 1, 35.0 / 15.0, 20.0 / 15.0});
+  }
   std::vector<pxd_fom_term> t;
-  for (const Row& r : rows)
+  for (const Row& r : table)
     if (r.i < ctx->P && r.j < ctx->P) t.push_back(pxd_fom_term{r.band, r.i, r.j, r.c, r.e});
   return pxd_set_fom(ctx, (int32_t)t.size(), t.data(), band.data());
 }

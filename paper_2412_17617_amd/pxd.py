@@ -20,6 +20,7 @@ PREC_FP64, PREC_MIXED32, PREC_MIXED_BF16, PREC_MIXED_F16 = 0, 1, 2, 3
 KIND_ALWAYS, KIND_INNER, KIND_INTER, KIND_PIXPORT, KIND_VIA = 0, 1, 2, 3, 4
 STATUS_OK, STATUS_FALLBACK, STATUS_NONFINITE, STATUS_SINGULAR, STATUS_SIZE = 0, 1, -1, -2, -3
 SCHED_AUTO, SCHED_FREQ_MAJOR, SCHED_SIZE_MAJOR = 0, 1, 2
+FOM_PAPER, FOM_REJ, FOM_ISO = 0, 1, 2
 SIDES = {"right": 0, "top": 1, "left": 2, "bottom": 3}
 
 
@@ -77,6 +78,7 @@ _SIGS = {
     "pxd_load_map": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_double]),
     "pxd_set_fom": (C.c_int, [_VP, C.c_int32, _VP, _VP]),
     "pxd_set_fom_paper": (C.c_int, [_VP]),
+    "pxd_set_fom_variant": (C.c_int, [_VP, C.c_int32]),
     "pxd_evaluate_flips": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pxd_evaluate_flips_device": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "pxd_expand": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
@@ -218,8 +220,9 @@ class Evaluator:
         kind, ca, cb, pbf, pl = problem.classification()
         self.load_map(problem.n_cells, kind, ca, cb, pbf, pl, z0)
 
-    def set_fom_paper(self):
-        self._c(lib().pxd_set_fom_paper(self._h))
+    def set_fom_paper(self, variant=0):
+        """variant: FOM_PAPER (Eqs. 8-9), FOM_REJ or FOM_ISO (Section III-D)."""
+        self._c(lib().pxd_set_fom_variant(self._h, variant))
 
     def set_fom(self, terms, band_of_freq):
         arr = (FomTerm * max(1, len(terms)))(*[FomTerm(*t) for t in terms])

@@ -190,3 +190,23 @@ def test_bad_arguments_return_codes():
         fresh.evaluate_flips(spec.base_map(), np.array([0, 0], np.int32), np.zeros(0, np.int32))
     assert e.value.code == pxd.ENOTLOADED
     fresh.close()
+
+
+@pytest.mark.parametrize("variant,name", [(pxd.FOM_REJ, "rej"), (pxd.FOM_ISO, "iso")])
+def test_fom_variants(variant, name):
+    """Section III-D term tables: the GPU FoM against the oracle's."""
+    from oracle import fom as ofom
+
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    S_o, _ = search.sweep(st, Z, base, off, cells, freqs)
+    F_o = np.array([ofom.fom(S_o[c], freqs, name) for c in range(len(off) - 1)])
+    ev, _ = make_evaluator(spec, Z, freqs)
+    ev.set_fom_paper(variant)
+    S, F, status, am = ev.evaluate_flips(base, off, cells)
+    ev.close()
+    assert np.abs(S - S_o).max() <= S_TOL
+    assert np.all(np.abs(F - F_o) <= FOM_RTOL * F_o)
+    check_argmin(am, F_o)

@@ -78,3 +78,20 @@ def test_clamp_keeps_fom_finite():
     f = np.array([5.5e9])
     S = np.zeros((1, 3, 3), dtype=complex)
     assert np.isfinite(fom.fom(S, f))
+
+
+def test_variant_tables_differ_from_eq8_by_exactly_their_terms():
+    """Section III-D: 'rej' swaps rw_s1/rw_s2 for their -45 dB forms, 'iso'
+    adds the isolation term over both passbands."""
+    spec = get_spec("batched20")
+    freqs = spec.freqs
+    rng = np.random.default_rng(3)
+    S = (rng.standard_normal((len(freqs), 3, 3)) + 1j * rng.standard_normal((len(freqs), 3, 3))) * 0.2
+    p1, p2, fi, fs = fom.band_sets(freqs)
+    base = fom.fom(S, freqs)
+    rw = [fom.rewards(S[k]) for k in range(len(freqs))]
+    iso_extra = sum(1.0 / rw[k]["oiiso"] for k in range(len(freqs)) if p1[k] or p2[k])
+    assert abs(fom.fom(S, freqs, "iso") - (base + iso_extra)) <= 1e-12 * base
+    rej = base - sum(1.0 / rw[k]["s2"] - 1.0 / rw[k]["s2rej"] for k in range(len(freqs)) if p1[k]) \
+        - sum(1.0 / rw[k]["s1"] - 1.0 / rw[k]["s1rej"] for k in range(len(freqs)) if p2[k])
+    assert abs(fom.fom(S, freqs, "rej") - rej) <= 1e-12 * base
