@@ -1,0 +1,87 @@
+"""Parity at the workloads' full sizes, on sampled outputs (GPU).
+
+The GPU evaluates every candidate of the full batch in the bench's launch
+configuration (persistent grid of 2 workgroups per CU, frequency-major
+items), at one frequency in the FoM's first passband; the oracle fills its
+own parent at that frequency and solves a seeded sample of the candidates
+one by one (LAPACK).  Tolerances as in the small-size tests: FP64 1e-10,
+the mixed forms 1e-4 (the metric's bar); per-frequency S only, so no FoM.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import efie, geometry, network, search
+from paper_2412_17617_amd import pxd
+from synth import get_spec, permutation
+
+pytestmark = pytest.mark.gpu
+
+
+def sampled(name, precisions, n_sample, f_target=5.5e9):
+    spec = get_spec(name)
+    fi = int(np.argmin(np.abs(spec.freqs - f_target)))
+    freqs = spec.freqs[fi:fi + 1]
+    st = geometry.build_structure(spec)
+    Z = efie.fill(st, freqs[0])[None]
+    base = spec.base_map()
+    off, cells = spec.flips()
+    C = len(off) - 1
+    pick = np.sort(permutation(C, 77)[:n_sample])
+    maps = search.candidate_maps(base, off, cells)
+    pl = search.port_lengths(st)
+    S_o = {}
+    for c in pick:
+        sel = st.active(maps[c])
+        S_o[c] = network.s_parameters(network.reduce_matrix(Z[0], sel), network.port_positions(sel, st.port_bf), pl,
+                                      spec.z0)
+    pb = pxd.Problem.from_spec(spec)
+    out = {}
+    for prec in precisions:
+        ev = pxd.Evaluator(precision=prec, ir_max_iter=40)
+        ev.load_parent(Z, freqs)
+        ev.load_problem(pb, spec.z0)
+        ev.set_fom_paper()
+        S, F, status, am = ev.evaluate_flips(base, off, cells)
+        stats = ev.stats()
+        ev.close()
+        dS = max(np.abs(S[c, 0] - S_o[c]).max() for c in pick)
+        print(f"{name} precision {prec}: N {stats['min_active']}-{stats['max_active']}, {C} candidates, sampled "
+              f"max |dS| {dS:.2e}, {stats['ir_iterations']} residuals, {stats['fallbacks']} fallbacks")
+        out[prec] = (S, status, dS)
+    return out
+
+
+def test_batched20_full_batch():
+    r = sampled("batched20", (pxd.PREC_FP64, pxd.PREC_MIXED32), 12)
+    assert r[pxd.PREC_FP64][2] <= 1e-10
+    assert r[pxd.PREC_MIXED32][2] <= 1e-4
+    for prec, (S, status, dS) in r.items():
+        assert np.all((status == 0) | (status == 1))
+
+
+def test_stress24_full_batch_every_precision():
+    precs = (pxd.PREC_FP64, pxd.PREC_MIXED32, pxd.PREC_MIXED_BF16, pxd.PREC_MIXED_F16)
+    r = sampled("stress24", precs, 6)
+    assert r[pxd.PREC_FP64][2] <= 1e-10
+    for prec in precs[1:]:
+        assert r[prec][2] <= 1e-4
+    for prec, (S, status, dS) in r.items():
+        assert np.all((status == 0) | (status == 1))
+
+
+def test_ceiling32_active_size_is_refused():
+    """The 32x32x3 stack's active sets (N ~ 3,000) exceed the kernels' 2,048
+    limit: the library refuses the batch instead of running it."""
+    spec = get_spec("ceiling32")
+    pb = pxd.Problem.from_spec(spec)
+    ev = pxd.Evaluator()
+    Z = np.zeros((1, pb.M, pb.M), np.complex128)
+    ev.load_parent(Z, spec.freqs[:1])
+    ev.load_problem(pb, spec.z0)
+    ev.set_fom_paper()
+    off = np.array([0, 1], np.int32)
+    with pytest.raises(pxd.PxdError) as e:
+        ev.evaluate_flips(spec.base_map(), off, np.array([0], np.int32))
+    assert e.value.code == pxd.ESHAPE
+    ev.close()
