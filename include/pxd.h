@@ -144,6 +144,9 @@ typedef struct pxd_stats {
   int32_t max_active;     /* largest active size N in the last call */
   int32_t min_active;
   double ms_expand, ms_solve, ms_fallback, ms_fom; /* stage times of the last call (events) */
+  double ms_base_inverse; /* low-rank calls: time of the base-map inverse (0 if reused) */
+  int32_t base_reused;    /* low-rank calls: 1 if the cached base inverse served the call */
+  int32_t reserved;
 } pxd_stats;
 
 int pxd_create(const pxd_options* opt, pxd_ctx** out);
@@ -186,6 +189,27 @@ int pxd_evaluate_flips(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, co
 int pxd_evaluate_flips_device(pxd_ctx* ctx, void* stream, const uint8_t* base_map, int32_t n_cand,
                               const int32_t* offsets, const int32_t* cells, int32_t n_flips, double* S_out,
                               double* fom_out, int32_t* status, int32_t* argmin_out);
+
+/* Flip candidates evaluated from the inverse of the base map instead of one
+ * dense factorisation each (a variant the paper does not use; it gives the
+ * S of Eqs. 6-7 for the candidate's Z_A of Eq. 5 up to rounding).  With
+ * G = Z_B^-1 for the base active set (port loads included), a candidate that
+ * drops the base functions R and adds the functions E is solved by block
+ * elimination: the removed functions by the Schur-complement identity for the
+ * inverse of a principal submatrix, the added ones by the block inverse of the
+ * bordered matrix.  Cost per (candidate, frequency): one pass over G per four
+ * added functions plus O((|R| + |E|)^3), against O(N^3) for a dense solve.
+ * G is computed in FP64 (F x N_B x N_B complex128 on the device) on the first
+ * call for a base map and reused while the base map, the parent and the map
+ * stay the same.  Candidates that drop more than 16 or add more than 8 base
+ * functions, relative to the base map, are solved by the dense FP64 path in the
+ * same call, whatever the context's precision (counted in pxd_stats.fallbacks).
+ * Z must be complex symmetric (Galerkin EFIE), which the identities use.
+ * Arguments, outputs and errors as for pxd_evaluate_flips; item status
+ * SINGULAR if the base matrix or one of the small blocks has a zero pivot. */
+int pxd_evaluate_flips_lowrank(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,
+                               const int32_t* cells, double* S_out, double* fom_out, int32_t* status,
+                               int32_t* argmin_out);
 
 /* Row a1 alone: active index sets (Eq. 3) of each candidate.  N_out n_cand;
  * idx_out n_cand x M (row c holds N_out[c] ascending indices).  Host buffers. */

@@ -88,9 +88,15 @@ struct pxd_ctx {
   std::vector<int> hNc;
   pxd_stats stats{};
   bool stats_pending_counts = false;
+  bool stats_lowrank = false;  // the last call was a low-rank one (stage events differ)
   // autotuning: tuned[precision][size class]; `forced` overrides during a tuning sweep
   Tuning tuned[kPrecisions][kSizeClasses];
   const Tuning* forced = nullptr;
+  // low-rank flip evaluation: inverse of the last base map, valid while gen == lr_gen
+  DevBuf lr_G, lr_IB, lr_NB, lr_pos, lr_bstat, lr_ws, lr_cnt;
+  std::vector<uint8_t> lr_map;
+  int lr_nb = 0;
+  long long gen = 0, lr_gen = -1;
 
   int fail(int rc, const std::string& m) {
     err = m;
@@ -142,7 +148,7 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   const bool mixed = ctx->opt.precision != PXD_PREC_FP64;
   const bool events = !capturing;
   const int M = ctx->M, F = ctx->F, P = ctx->P;
-  if (events) ctx->stats = pxd_stats{};
+  if (events) ctx->stats = pxd_stats{}, ctx->stats_lowrank = false;
   if (C == 0) return PXD_OK;
   HIPCHK(ctx, b.Nc.ensure(sizeof(int) * C));
   HIPCHK(ctx, b.Ilist.ensure(sizeof(int) * (size_t)C * M));
@@ -280,6 +286,156 @@ int download(pxd_ctx* ctx, int C, double* S_out, double* fom_out, int32_t* statu
   return PXD_OK;
 }
 
+// Low-rank evaluation of C flip candidates of one base map (host inputs): the
+// base inverse (unless cached), the low-rank kernel, the dense FP64 kernel on
+// the items beyond the rank limits, then FoM and argmin.
+int evaluate_lowrank(pxd_ctx* ctx, const uint8_t* base_map, int C, const int32_t* offsets, const int32_t* cells) {
+  if (!ctx->Z128.p) return ctx->fail(PXD_ENOTLOADED, "parent matrices not loaded");
+  if (!ctx->terms.p) return ctx->fail(PXD_ENOTLOADED, "FoM table not set");
+  hipStream_t s = ctx->stream;
+  const int M = ctx->M, F = ctx->F, P = ctx->P;
+  const int nf = offsets[C];
+  ctx->stats = pxd_stats{};
+  if (C == 0) return PXD_OK;
+  HIPCHK(ctx, ctx->base.ensure(ctx->n_cells));
+  HIPCHK(ctx, ctx->off.ensure(sizeof(int) * (C + 1)));
+  HIPCHK(ctx, ctx->cells.ensure(sizeof(int) * std::max(1, nf)));
+  HIPCHK(ctx, ctx->S.ensure(sizeof(double2) * (size_t)C * F * P * P));
+  HIPCHK(ctx, ctx->fom.ensure(sizeof(double) * C));
+  HIPCHK(ctx, ctx->cand_status.ensure(sizeof(int) * C));
+  HIPCHK(ctx, ctx->argmin.ensure(sizeof(int)));
+  EvalBufs& b = ctx->eb;
+  HIPCHK(ctx, b.Nc.ensure(sizeof(int) * C));
+  HIPCHK(ctx, b.Ilist.ensure(sizeof(int) * (size_t)C * M));
+  HIPCHK(ctx, b.order.ensure(sizeof(int) * C));
+  HIPCHK(ctx, b.counter.ensure(sizeof(int) * 8));
+  HIPCHK(ctx, b.item_status.ensure(sizeof(int) * (size_t)C * F));
+  HIPCHK(ctx, b.fb_list.ensure(sizeof(int) * (size_t)C * F));
+  HIPCHK(ctx, ctx->lr_IB.ensure(sizeof(int) * M));
+  HIPCHK(ctx, ctx->lr_NB.ensure(sizeof(int)));
+  HIPCHK(ctx, ctx->lr_pos.ensure(sizeof(int) * M));
+  HIPCHK(ctx, ctx->lr_bstat.ensure(sizeof(int) * F));
+  HIPCHK(ctx, ctx->lr_cnt.ensure(sizeof(int)));
+  HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->base.p, base_map, ctx->n_cells, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->off.p, offsets, sizeof(int) * (C + 1), hipMemcpyHostToDevice, s));
+  if (nf > 0) HIPCHK(ctx, hipMemcpyAsync(ctx->cells.p, cells, sizeof(int) * nf, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, pxd::launch_expand(s, ctx->base.as<uint8_t>(), ctx->n_cells, 0, ctx->off.as<int>(),
+                                 ctx->cells.as<int>(), C, ctx->cell_a.as<int>(), ctx->cell_b.as<int>(), M,
+                                 b.Nc.as<int>(), b.Ilist.as<int>()));
+  HIPCHK(ctx, pxd::launch_order(s, b.Nc.as<int>(), C, b.order.as<int>()));
+  const bool reuse = ctx->lr_gen == ctx->gen && ctx->lr_G.p &&
+                     ctx->lr_map.size() == (size_t)ctx->n_cells &&
+                     std::memcmp(ctx->lr_map.data(), base_map, ctx->n_cells) == 0;
+  if (!reuse)  // the base map's own active set, as a one-map batch
+    HIPCHK(ctx, pxd::launch_expand(s, ctx->base.as<uint8_t>(), ctx->n_cells, (size_t)ctx->n_cells, nullptr, nullptr,
+                                   1, ctx->cell_a.as<int>(), ctx->cell_b.as<int>(), M, ctx->lr_NB.as<int>(),
+                                   ctx->lr_IB.as<int>()));
+  ctx->hNc.resize(C + 1);
+  HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data(), b.Nc.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data() + C, ctx->lr_NB.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  const int nmax = *std::max_element(ctx->hNc.begin(), ctx->hNc.begin() + C);
+  const int nmin = *std::min_element(ctx->hNc.begin(), ctx->hNc.begin() + C);
+  const int NB = reuse ? ctx->lr_nb : ctx->hNc[C];
+  if (nmin < P || NB < P) return ctx->fail(PXD_ESHAPE, "candidate with fewer active functions than ports");
+  if (nmax > 2048 || NB > 2048) return ctx->fail(PXD_ESHAPE, "active size above 2048 is not supported");
+  HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+  if (!reuse) {
+    ctx->lr_gen = -1;  // invalid until the inverse below is enqueued
+    HIPCHK(ctx, pxd::launch_positions(s, ctx->lr_IB.as<int>(), NB, M, ctx->lr_pos.as<int>()));
+    HIPCHK(ctx, ctx->lr_G.ensure(sizeof(double2) * (size_t)F * NB * NB));
+    const int ld = (2 * NB + 3) / 4 * 4;
+    const size_t slot = ((size_t)NB * ld * sizeof(double2) + 255) / 256 * 256;
+    const int grid = std::min(F, ctx->n_cu * 2);
+    HIPCHK(ctx, ctx->lr_ws.ensure(slot * grid));
+    HIPCHK(ctx, pxd::launch_fill_int(s, ctx->lr_cnt.as<int>(), 1, 0));
+    pxd::InvParams ip{};
+    ip.Z128 = ctx->Z128.as<double2>();
+    ip.M = M, ip.F = F, ip.P = P;
+    ip.IB = ctx->lr_IB.as<int>();
+    ip.N = NB;
+    ip.port_len = ctx->plen.as<double>();
+    ip.z0 = ctx->z0;
+    ip.ws = ctx->lr_ws.as<char>();
+    ip.slot_bytes = slot;
+    ip.ld = ld;
+    ip.G = ctx->lr_G.as<double2>();
+    ip.status = ctx->lr_bstat.as<int>();
+    ip.counter = ctx->lr_cnt.as<int>();
+    HIPCHK(ctx, pxd::launch_base_inverse(s, ip, grid));
+    ctx->lr_map.assign(base_map, base_map + ctx->n_cells);
+    ctx->lr_nb = NB;
+    ctx->lr_gen = ctx->gen;
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->ev[5], s));
+  int* cnt = b.counter.as<int>();  // [0] work, [1] items beyond the rank limits, [3] their dense work
+  HIPCHK(ctx, pxd::launch_fill_int(s, cnt, 8, 0));
+  pxd::LrParams lp{};
+  lp.Z128 = ctx->Z128.as<double2>();
+  lp.M = M, lp.F = F, lp.P = P, lp.C = C;
+  lp.Nc = b.Nc.as<int>();
+  lp.Ilist = b.Ilist.as<int>();
+  lp.order = b.order.as<int>();
+  lp.IB = ctx->lr_IB.as<int>();
+  lp.NB = NB;
+  lp.pos_of = ctx->lr_pos.as<int>();
+  lp.G = ctx->lr_G.as<double2>();
+  lp.base_status = ctx->lr_bstat.as<int>();
+  lp.port_len = ctx->plen.as<double>();
+  lp.z0 = ctx->z0;
+  lp.S = ctx->S.as<double2>();
+  lp.status = b.item_status.as<int>();
+  lp.counter = cnt;
+  lp.fb_list = b.fb_list.as<int>();
+  lp.fb_count = cnt + 1;
+  const long long items = (long long)C * F;
+  HIPCHK(ctx, pxd::launch_lowrank(s, lp, (int)std::min<long long>(items, (long long)ctx->n_cu * 2)));
+  HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+  int n_fb = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&n_fb, cnt + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (n_fb > 0) {  // the dense FP64 kernel on the listed items
+    const Tuning tune = resolve(ctx, pxd::rows_per_thread(nmax));
+    const pxd::SlotLayout lay = pxd::slot_layout(nmax, P, false);
+    const int grid = std::min(n_fb, ctx->n_cu * tune.wg_per_cu);
+    HIPCHK(ctx, b.ws.ensure(lay.bytes * (size_t)grid));
+    pxd::EvalParams ep{};
+    ep.Z128 = ctx->Z128.as<double2>();
+    ep.M = M, ep.F = F, ep.P = P, ep.C = C;
+    ep.Nc = b.Nc.as<int>();
+    ep.Ilist = b.Ilist.as<int>();
+    ep.order = b.order.as<int>();
+    ep.port_len = ctx->plen.as<double>();
+    ep.z0 = ctx->z0;
+    ep.n_items = n_fb;
+    ep.item_list = b.fb_list.as<int>();
+    ep.counter = cnt + 3;
+    ep.ws = b.ws.as<char>();
+    ep.slot_bytes = lay.bytes;
+    ep.ld = lay.ld;
+    ep.nmax = nmax;
+    ep.S = ctx->S.as<double2>();
+    ep.status = b.item_status.as<int>();
+    ep.schedule = PXD_SCHED_FREQ_MAJOR;
+    HIPCHK(ctx, pxd::launch_eval_plain(s, ep, grid, tune.half_sb));
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+  HIPCHK(ctx, pxd::launch_fom(s, ctx->S.as<double2>(), C, F, P, ctx->terms.as<pxd_fom_term>(),
+                              ctx->term_fac.as<double>(), ctx->n_terms, ctx->band.as<int8_t>(),
+                              b.item_status.as<int>(), ctx->fom.as<double>(), ctx->cand_status.as<int>()));
+  HIPCHK(ctx, pxd::launch_argmin(s, ctx->fom.as<double>(), C, ctx->argmin.as<int>()));
+  HIPCHK(ctx, hipEventRecord(ctx->ev[4], s));
+  ctx->stats.items = items;
+  ctx->stats.fallbacks = n_fb;
+  ctx->stats.max_active = nmax;
+  ctx->stats.min_active = nmin;
+  ctx->stats.base_reused = reuse ? 1 : 0;
+  ctx->stats_pending_counts = false;
+  ctx->stats_lowrank = true;
+  return PXD_OK;
+}
+
 }  // namespace
 
 namespace pxd {
@@ -341,6 +497,8 @@ void pxd_destroy(pxd_ctx* ctx) {
                     &ctx->band, &ctx->base, &ctx->off, &ctx->cells, &ctx->S, &ctx->cand_status, &ctx->fom,
                     &ctx->argmin})
     b->release();
+  for (DevBuf* b : {&ctx->lr_G, &ctx->lr_IB, &ctx->lr_NB, &ctx->lr_pos, &ctx->lr_bstat, &ctx->lr_ws, &ctx->lr_cnt})
+    b->release();
   ctx->eb.release();
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -366,6 +524,7 @@ int pxd_load_parent(pxd_ctx* ctx, int32_t M, int32_t F, const double* freqs_hz, 
   ctx->M = M;
   ctx->F = F;
   ctx->freqs.assign(freqs_hz, freqs_hz + F);
+  ++ctx->gen;
   ctx->terms.release();  // band ids depend on the frequency grid
   ctx->n_terms = 0;
   return PXD_OK;
@@ -397,6 +556,7 @@ int pxd_load_map(pxd_ctx* ctx, int32_t n_cells, int32_t M, const uint8_t* kind, 
   ctx->P = P;
   ctx->z0 = z0;
   ctx->port_len.assign(port_len, port_len + P);
+  ++ctx->gen;
   return PXD_OK;
 }
 
@@ -477,6 +637,20 @@ int pxd_evaluate_flips(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, co
   if (rc) return rc;
   HIPCHK(ctx, hipSetDevice(ctx->opt.device));
   rc = upload_and_evaluate(ctx, base_map, 0, n_cand, offsets, cells);
+  if (rc) return rc;
+  return download(ctx, n_cand, S_out, fom_out, status, argmin_out);
+}
+
+int pxd_evaluate_flips_lowrank(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,
+                               const int32_t* cells, double* S_out, double* fom_out, int32_t* status,
+                               int32_t* argmin_out) {
+  if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  if (!base_map) return ctx->fail(PXD_EINVAL, "base_map is NULL");
+  if (!ctx->cell_a.p) return ctx->fail(PXD_ENOTLOADED, "pixel-to-RWG map not loaded");
+  int rc = check_flips(ctx, n_cand, offsets, cells);
+  if (rc) return rc;
+  HIPCHK(ctx, hipSetDevice(ctx->opt.device));
+  rc = evaluate_lowrank(ctx, base_map, n_cand, offsets, cells);
   if (rc) return rc;
   return download(ctx, n_cand, S_out, fom_out, status, argmin_out);
 }
@@ -731,7 +905,14 @@ int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out) {
   if (ctx->stats.items > 0 && hipEventSynchronize(ctx->ev[4]) == hipSuccess) {
     float a = 0, b = 0, c = 0;
     if (hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]) == hipSuccess) out->ms_expand = a;
-    if (hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]) == hipSuccess) out->ms_solve = b;
+    if (ctx->stats_lowrank) {
+      float g = 0, h = 0;
+      if (hipEventElapsedTime(&g, ctx->ev[1], ctx->ev[5]) == hipSuccess) out->ms_base_inverse = g;
+      if (hipEventElapsedTime(&h, ctx->ev[5], ctx->ev[2]) == hipSuccess) out->ms_solve = h;
+      if (hipEventElapsedTime(&h, ctx->ev[2], ctx->ev[3]) == hipSuccess) out->ms_fallback = h;
+    } else if (hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]) == hipSuccess) {
+      out->ms_solve = b;
+    }
     if (hipEventElapsedTime(&c, ctx->ev[3], ctx->ev[4]) == hipSuccess) out->ms_fom = c;
     float d = 0;
     if (ctx->stats_pending_counts && hipEventElapsedTime(&d, ctx->ev[2], ctx->ev[3]) == hipSuccess) {

@@ -928,6 +928,96 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_plain(EvalParams p) {
 }
 
 
+// ------------------------------------------------------------------ base inverse
+
+// G_f = Z_B(f)^-1 of the base map's active set (port loads included), one
+// item per frequency: [Z_B | I] is factored with the two-level LU over all N
+// columns, then U X = (L^-1 P) is solved upwards, one thread per column of X
+// in blocks of 8 rows, and X is written to G (F x N x N, row-major; Z_B is
+// symmetric, so G is too).
+template <int Q, int SB>
+__global__ __launch_bounds__(kThreads, 2) void k_base_inverse(InvParams p) {
+  using T = double2;
+  __shared__ LuShared<double> sm;
+  __shared__ int sI[kThreads * Q];
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  const int N = p.N, ld = p.ld;
+  T* W = reinterpret_cast<T*>(p.ws + (size_t)blockIdx.x * p.slot_bytes);
+  for (int s = tid; s < N && s < kThreads * Q; s += kThreads) sI[s] = p.IB[s];
+  __syncthreads();
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(p.counter, 1);
+    __syncthreads();
+    const int f = s_item;
+    __syncthreads();
+    if (f >= p.F) break;
+    if (N > kThreads * Q) {
+      if (tid == 0) p.status[f] = PXD_STATUS_SIZE;
+      continue;
+    }
+    if (tid == 0) sm.bad = 0;
+    const double2* Zf = p.Z128 + (size_t)f * p.M * p.M;
+    for (int r = tid >> 6; r < N; r += kWaves) {
+      const double2* zrow = Zf + (size_t)sI[r] * p.M;
+      for (int c = tid & 63; c < N; c += 64) {
+        W[(size_t)r * ld + c] = zrow[sI[c]];
+        W[(size_t)r * ld + N + c] = T{(r == c) ? 1.0 : 0.0, 0.0};
+      }
+    }
+    __syncthreads();
+    if (tid < p.P) {
+      const int r = N - p.P + tid;
+      W[(size_t)r * ld + r].x += p.z0 * p.port_len[tid] * p.port_len[tid];
+    }
+    __syncthreads();
+    lu_factor<double, Q, SB, KB_PLAIN, 1>(W, ld, N, N, 2 * N, sm, nullptr);
+    constexpr int B = 8;
+    for (int col = N + tid; col < 2 * N; col += kThreads) {
+      for (int b1 = N; b1 > 0; b1 -= B) {
+        const int b0 = max(0, b1 - B), nb = b1 - b0;
+        T u[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) u[i] = (i < nb) ? W[(size_t)(b0 + i) * ld + col] : T{0, 0};
+        for (int j = b1; j < N; ++j) {  // solved rows below the block
+          const T xj = W[(size_t)j * ld + col];
+#pragma unroll
+          for (int i = 0; i < B; ++i)
+            if (i < nb) u[i] = cfms(u[i], W[(size_t)(b0 + i) * ld + j], xj);
+        }
+#pragma unroll
+        for (int i = B - 1; i >= 0; --i) {
+          if (i < nb) {
+#pragma unroll
+            for (int jj = i + 1; jj < B; ++jj)
+              if (jj < nb) u[i] = cfms(u[i], W[(size_t)(b0 + i) * ld + b0 + jj], u[jj]);
+            u[i] = cmul(u[i], crecip(W[(size_t)(b0 + i) * ld + b0 + i]));
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+          if (i < nb) W[(size_t)(b0 + i) * ld + col] = u[i];
+      }
+    }
+    __syncthreads();
+    double2* G = p.G + (size_t)f * N * N;
+    for (int r = tid >> 6; r < N; r += kWaves)
+      for (int c = tid & 63; c < N; c += 64) G[(size_t)r * N + c] = W[(size_t)r * ld + N + c];
+    if (tid == 0) p.status[f] = sm.bad ? PXD_STATUS_SINGULAR : PXD_STATUS_OK;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_base_inverse(hipStream_t s, const InvParams& p, int grid) {
+  const int Q = rows_per_thread(p.N);
+  if (Q <= 1) hipLaunchKernelGGL((k_base_inverse<1, 16>), dim3(grid), dim3(kThreads), 0, s, p);
+  else if (Q <= 2) hipLaunchKernelGGL((k_base_inverse<2, 8>), dim3(grid), dim3(kThreads), 0, s, p);
+  else if (Q <= 4) hipLaunchKernelGGL((k_base_inverse<4, 4>), dim3(grid), dim3(kThreads), 0, s, p);
+  else if (Q <= 8) hipLaunchKernelGGL((k_base_inverse<8, 2>), dim3(grid), dim3(kThreads), 0, s, p);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ mixed precision
 
 // out[jr] -= sum_j row[j] y[j * P + jr] for j < kb (kb <= NB), jr < P: the

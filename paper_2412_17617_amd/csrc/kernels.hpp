@@ -45,6 +45,47 @@ struct EvalParams {
 #define PXD_HALF_BF16 1
 #define PXD_HALF_F16 2
 
+// Base-map inverse: one item per frequency.
+struct InvParams {
+  const double2* Z128;  // F x M x M parents
+  int M, F, P;
+  const int* IB;        // base active list (N ascending parent indices, ports last)
+  int N;
+  const double* port_len;
+  double z0;
+  char* ws;             // one N x ld complex128 slot per workgroup (ld >= 2 N)
+  size_t slot_bytes;
+  int ld;
+  double2* G;           // F x N x N output
+  int* status;          // F
+  int* counter;         // work counter (zeroed before the launch)
+};
+hipError_t launch_base_inverse(hipStream_t s, const InvParams& p, int grid);
+
+// Low-rank evaluation of flip candidates from the base inverse: one item per
+// (candidate, frequency), frequency-major.
+struct LrParams {
+  const double2* Z128;  // F x M x M parents
+  int M, F, P, C;
+  const int* Nc;        // candidate active sizes
+  const int* Ilist;     // C x M candidate active lists
+  const int* order;     // candidate order
+  const int* IB;        // base active list (NB entries, ports last)
+  int NB;
+  const int* pos_of;    // M: base position of each parent function, -1 if inactive
+  const double2* G;     // F x NB x NB base inverses
+  const int* base_status;  // F
+  const double* port_len;
+  double z0;
+  double2* S;           // C x F x P x P
+  int* status;          // C x F
+  int* counter;
+  int* fb_list;         // items beyond the low-rank limits, for the dense FP64 path
+  int* fb_count;
+};
+hipError_t launch_positions(hipStream_t s, const int* IB, int NB, int M, int* pos_of);
+hipError_t launch_lowrank(hipStream_t s, const LrParams& p, int grid);
+
 // Per-slot layout of the workspace (byte offsets).
 struct SlotLayout {
   size_t w_off, piv_off, x_off, bytes;

@@ -56,6 +56,7 @@ class Stats(C.Structure):
         ("items", C.c_int64), ("fallbacks", C.c_int64), ("ir_iterations", C.c_int64),
         ("max_active", C.c_int32), ("min_active", C.c_int32),
         ("ms_expand", C.c_double), ("ms_solve", C.c_double), ("ms_fallback", C.c_double), ("ms_fom", C.c_double),
+        ("ms_base_inverse", C.c_double), ("base_reused", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ _SIGS = {
     "pxd_set_fom_paper": (C.c_int, [_VP]),
     "pxd_set_fom_variant": (C.c_int, [_VP, C.c_int32]),
     "pxd_evaluate_flips": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "pxd_evaluate_flips_lowrank": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pxd_evaluate_flips_device": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "pxd_expand": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "pxd_gather": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP]),
@@ -240,6 +242,20 @@ class Evaluator:
         am = np.zeros(1, np.int32)
         self._c(lib().pxd_evaluate_flips(self._h, _ptr(base), n, _ptr(off), _ptr(cl if len(cl) else
                                          np.zeros(1, np.int32)), _ptr(S), _ptr(fom), _ptr(st), _ptr(am)))
+        return S, fom, st, int(am[0])
+
+    def evaluate_flips_lowrank(self, base_map, offsets, cells, want_S=True):
+        """As evaluate_flips, solved from the cached inverse of the base map."""
+        base = np.ascontiguousarray(base_map, np.uint8)
+        off = np.ascontiguousarray(offsets, np.int32)
+        cl = np.ascontiguousarray(cells, np.int32)
+        n = len(off) - 1
+        S = np.empty((n, self.F, self.P, self.P), np.complex128) if want_S else None
+        fom = np.empty(n, np.float64)
+        st = np.empty(n, np.int32)
+        am = np.zeros(1, np.int32)
+        self._c(lib().pxd_evaluate_flips_lowrank(self._h, _ptr(base), n, _ptr(off), _ptr(cl if len(cl) else
+                                                 np.zeros(1, np.int32)), _ptr(S), _ptr(fom), _ptr(st), _ptr(am)))
         return S, fom, st, int(am[0])
 
     def evaluate_flips_device(self, stream, base_map, offsets, cells, S_out, fom_out, status_out=None,

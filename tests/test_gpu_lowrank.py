@@ -1,0 +1,162 @@
+"""GPU parity of the low-rank flip evaluation against the oracle, through the C ABI.
+
+The low-rank entry point solves each candidate from the FP64 inverse G of the
+base map's Z_B by block elimination; the oracle solves each candidate's Z_A
+(Eq. 5) with LAPACK.  Both are exact up to rounding.  Tolerance: G carries a
+relative error ~kappa(Z_B) eps; the removed-function update divides by
+G_RR and the bordering by its Schur complement, whose conditioning is bounded
+by that of the candidate's Z_A, so |dS| <= ~kappa(Z_B) kappa(Z_A) eps
+<= 1e4 * 1e4 * 1.1e-16 ~ 1e-8 on these workloads.  1e-8 is the bar (measured
+values sit well below it); the FoM's relative tolerance follows as in the
+dense tests (2 |dS| / |S|min with |S|min ~ 1e-5 gives ~2e-3; 1e-4 relative is
+used, inside measured margins).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import efie, geometry, network, search
+from paper_2412_17617_amd import pxd
+from synth import bernoulli_map, get_spec, permutation
+
+from gpu_common import make_evaluator, oracle_active_sets, oracle_parent
+
+pytestmark = pytest.mark.gpu
+
+S_TOL = 1e-8
+FOM_RTOL = 1e-4
+KR_MAX, KE_MAX = 16, 8  # removed / added functions the low-rank kernel handles
+
+
+def flip_groups(groups):
+    off = np.zeros(len(groups) + 1, np.int32)
+    off[1:] = np.cumsum([len(g) for g in groups])
+    cells = np.concatenate([np.asarray(g, np.int32) for g in groups]) if off[-1] else np.zeros(0, np.int32)
+    return off, cells
+
+
+def over_limit(st, base, off, cells):
+    """Candidates whose active set differs from the base map's by more than
+    the kernel's limits (the oracle's own active sets)."""
+    b = set(network.support(st.active(base)).tolist())
+    out = []
+    for a in oracle_active_sets(st, base, off, cells):
+        a = set(a.tolist())
+        out.append(len(b - a) > KR_MAX or len(a - b) > KE_MAX)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("name", ["tiny4x2", "small6x3"])
+def test_single_flips_match_oracle(name):
+    spec = get_spec(name)
+    st, Z, freqs = oracle_parent(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
+    ev, _ = make_evaluator(spec, Z, freqs)
+    S, F, status, am = ev.evaluate_flips_lowrank(base, off, cells)
+    stats = ev.stats()
+    S_d, F_d, _, _ = ev.evaluate_flips(base, off, cells)
+    ev.close()
+    dS = np.abs(S - S_o).max()
+    print(f"{name}: N {stats['min_active']}-{stats['max_active']}, max |dS| vs oracle {dS:.2e}, "
+          f"vs dense GPU {np.abs(S - S_d).max():.2e}, fallbacks {stats['fallbacks']}")
+    assert np.all(status == 0)
+    assert dS <= S_TOL
+    assert np.all(np.abs(F - F_o) <= FOM_RTOL * np.abs(F_o))
+    order = np.argsort(F_o, kind="stable")
+    assert am == order[0] or abs(F_o[am] - F_o[order[0]]) <= FOM_RTOL * F_o[order[0]]
+
+
+def test_multi_flips_empty_and_fallback():
+    """No flips (the base map itself), pairs and triples, a flip that toggles
+    back, and candidates far from the base that exceed the low-rank limits
+    and go to the dense FP64 kernel in the same call."""
+    spec = get_spec("small6x3")
+    st, Z, freqs = oracle_parent(spec, (0, 2, 4))
+    n = spec.n_cells
+    base = bernoulli_map(n, 0.55, 11)
+    rng = np.random.default_rng(5)
+    groups = [[], [4, 4], [0, 1], [7, 20, 33], list(rng.choice(n, 4, replace=False)), list(range(n)),
+              list(range(0, n, 2)), [n - 1]]
+    off, cells = flip_groups(groups)
+    S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
+    over = over_limit(st, base, off, cells)
+    assert over.any() and not over.all()
+    ev, _ = make_evaluator(spec, Z, freqs)
+    S, F, status, am = ev.evaluate_flips_lowrank(base, off, cells)
+    stats = ev.stats()
+    ev.close()
+    print(f"max |dS| {np.abs(S - S_o).max():.2e}; over the limits: {np.flatnonzero(over)}; "
+          f"fallbacks {stats['fallbacks']}")
+    assert np.all(status == 0)
+    assert np.abs(S - S_o).max() <= S_TOL
+    assert np.all(np.abs(F - F_o) <= FOM_RTOL * np.abs(F_o))
+    assert stats["fallbacks"] == int(over.sum()) * len(freqs)
+
+
+def test_base_inverse_cache():
+    """The base inverse is reused only for the same base map, parent and map."""
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    ev, _ = make_evaluator(spec, Z, freqs)
+    S1, F1, _, _ = ev.evaluate_flips_lowrank(base, off, cells)
+    assert ev.stats()["base_reused"] == 0
+    S2, F2, _, _ = ev.evaluate_flips_lowrank(base, off, cells)
+    assert ev.stats()["base_reused"] == 1
+    assert np.array_equal(S1, S2) and np.array_equal(F1, F2)
+    # a new base map: recomputed, and still the oracle's answer
+    base2 = base.copy()
+    base2[3] ^= 1
+    S3, _, _, _ = ev.evaluate_flips_lowrank(base2, off, cells)
+    assert ev.stats()["base_reused"] == 0
+    S3_o, _ = search.sweep(st, Z, base2, off, cells, freqs)
+    assert np.abs(S3 - S3_o).max() <= S_TOL
+    # a reloaded parent (scaled: S changes) invalidates the cache
+    ev.load_parent(Z * 1.5, freqs)
+    ev.set_fom_paper()
+    S4, _, _, _ = ev.evaluate_flips_lowrank(base2, off, cells)
+    assert ev.stats()["base_reused"] == 0
+    S4_o, _ = search.sweep(st, Z * 1.5, base2, off, cells, freqs)
+    assert np.abs(S4 - S4_o).max() <= S_TOL
+    ev.close()
+
+
+def test_full_batch_sampled():
+    """20 x 20 x 2 batch (every single flip of the base map) at one frequency
+    in the first passband: all candidates on the GPU, a seeded sample by the
+    oracle one by one."""
+    spec = get_spec("batched20")
+    fi = int(np.argmin(np.abs(spec.freqs - 5.5e9)))
+    freqs = spec.freqs[fi:fi + 1]
+    st = geometry.build_structure(spec)
+    Z = efie.fill(st, freqs[0])[None]
+    base = spec.base_map()
+    off, cells = spec.flips()
+    C = len(off) - 1
+    pick = np.sort(permutation(C, 78)[:10])
+    maps = search.candidate_maps(base, off, cells)
+    pl = search.port_lengths(st)
+    pb = pxd.Problem.from_spec(spec)
+    ev = pxd.Evaluator()
+    ev.load_parent(Z, freqs)
+    ev.load_problem(pb, spec.z0)
+    ev.set_fom_paper()
+    S, F, status, am = ev.evaluate_flips_lowrank(base, off, cells)
+    stats = ev.stats()
+    S_d, _, _, _ = ev.evaluate_flips(base, off, cells)
+    ev.close()
+    dS = 0.0
+    for c in pick:
+        sel = st.active(maps[c])
+        S_o = network.s_parameters(network.reduce_matrix(Z[0], sel), network.port_positions(sel, st.port_bf), pl,
+                                   spec.z0)
+        dS = max(dS, np.abs(S[c, 0] - S_o).max())
+    print(f"batched20: N_B {stats['max_active']}, {C} candidates, sampled max |dS| {dS:.2e}, "
+          f"max |dS| vs dense GPU {np.abs(S - S_d).max():.2e}, fallbacks {stats['fallbacks']}, "
+          f"base inverse {stats['ms_base_inverse']:.1f} ms, low-rank {stats['ms_solve']:.1f} ms")
+    assert np.all(status == 0)
+    assert dS <= S_TOL
+    assert np.abs(S - S_d).max() <= S_TOL
