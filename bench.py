@@ -109,6 +109,57 @@ def cpu_baseline(spec, gpu_S, sample_c, seconds):
     return {"value": value, "unit": "evals/s", "cores": int(cores), "kind": "oracle", "sample": sample}, dS
 
 
+def lowrank_leg(args, pxd, spec, pb, Z, base, off, cells, results):
+    """The same batch through the low-rank flip evaluation (FP64, from the
+    cached inverse of the base map), host buffers in and out."""
+    C = len(off) - 1
+    ev = pxd.Evaluator(device=0, precision=pxd.PREC_FP64)
+    ev.load_parent(Z, spec.freqs)
+    ev.load_problem(pb, spec.z0)
+    ev.set_fom_paper()
+    Nc, idx = ev.expand(base, off, cells)
+    NB, idx_b = ev.expand(base, np.zeros(2, np.int32), np.zeros(0, np.int32))
+    bset = set(idx_b[0].tolist())
+    added = np.array([len(set(idx[c].tolist()) - bset) for c in range(C)])
+    t0 = time.perf_counter()
+    S, fom, st, am = ev.evaluate_flips_lowrank(base, off, cells)
+    first_ms = (time.perf_counter() - t0) * 1e3
+    s_first = ev.stats()
+    log(f"[lowrank] first call {first_ms:.1f} ms (base inverse {s_first['ms_base_inverse']:.1f} ms, "
+        f"N_B = {NB[0]}, {s_first['fallbacks']} dense items)")
+    t0 = time.perf_counter()
+    k_ms = []
+    for i in range(args.steps):
+        S, fom, st, am = ev.evaluate_flips_lowrank(base, off, cells)
+        k_ms.append(ev.stats()["ms_solve"])
+        log(f"[lowrank] step {i + 1}/{args.steps}: kernel {k_ms[-1]:.2f} ms")
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    stats = ev.stats()
+    ev.close()
+    # algorithmic bytes of the low-rank kernel: one pass over G (N_B^2 complex128)
+    # per four added functions, per (candidate, frequency)
+    passes = float(np.sum((added + 3) // 4)) * spec.n_freq
+    g_bytes = passes * float(NB[0]) ** 2 * 16
+    k = float(np.mean(k_ms))
+    out = {
+        "value": C / (ms / 1e3), "unit": "evals/s", "ms_per_step": ms, "kernel_ms": k,
+        "first_call_ms": first_ms, "ms_base_inverse": s_first["ms_base_inverse"],
+        "base_reused": int(stats["base_reused"]), "dense_fallback_items": int(stats["fallbacks"]),
+        "status_errors": int(np.count_nonzero(st != 0)),
+        "io": "host buffers (PCIe copies of flips and S inside the timed step)",
+        "g_stream": {"bytes_per_launch": g_bytes, "achieved_GBps": g_bytes / (k / 1e3) / 1e9,
+                     "basis": "N_B^2 x 16 B per pass, ceil(added / 4) passes per (candidate, frequency)"},
+    }
+    if "fp64" in results:
+        f64 = results["fp64"]
+        sc = f64["sample_c"]
+        out["max_dS_vs_fp64_plain"] = float(np.abs(S[sc] - f64["S_sample"]).max())
+        out["argmin_equal_fp64_plain"] = bool(am == f64["am"])
+        out["fom_rel_dev_vs_fp64_plain"] = float(np.max(np.abs(fom - f64["fom"]) / f64["fom"]))
+        out["speedup_vs_fp64_plain"] = out["value"] / f64["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +169,7 @@ def main():
     ap.add_argument("--precision", default="both", choices=sorted(PEAK_TFLOPS) + ["both"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank flip evaluation leg")
     ap.add_argument("--fill-threads", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device, a reference kernel of known traffic for "
@@ -147,8 +199,22 @@ def main():
     pb = pxd.Problem.from_spec(spec)
     t = time.time()
     Z = pb.fill(freqs, n_threads=args.fill_threads)
-    log(f"parent fill (host, {args.fill_threads} threads): M = {pb.M}, {time.time() - t:.1f} s")
+    host_fill_s = time.time() - t
+    log(f"parent fill (host, {args.fill_threads} threads): M = {pb.M}, {host_fill_s:.1f} s")
     dev = torch.device("cuda:0")
+    Zd = torch.empty((spec.n_freq, pb.M, pb.M), dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    t = time.time()
+    pb.fill_device(freqs, Zd)
+    torch.cuda.synchronize()
+    gpu_fill_s = time.time() - t
+    chk = list(range(0, spec.n_freq, max(1, spec.n_freq // 4)))
+    fill_dev = float(max(np.abs(Zd[f].cpu().numpy() - Z[f]).max() / np.abs(Z[f]).max() for f in chk))
+    del Zd
+    log(f"parent fill (GPU): {gpu_fill_s * 1e3:.0f} ms, max |dZ| / max |Z| vs host fill {fill_dev:.1e}")
+    parent_fill = {"gpu_s": gpu_fill_s, "host_s": host_fill_s, "host_threads": args.fill_threads,
+                   "speedup": host_fill_s / gpu_fill_s, "max_rel_dZ_vs_host": fill_dev,
+                   "frequencies": spec.n_freq, "M": pb.M}
     base = spec.base_map()
     off, cells = spec.flips()
     C = len(off) - 1
@@ -211,6 +277,7 @@ def main():
         results[mode]["S_sample"] = torch.view_as_complex(S_out[sample_c].contiguous()).cpu().numpy()
         ev.close()
         del S_out
+    lowrank = None if args.no_lowrank else lowrank_leg(args, pxd, spec, pb, Z, base, off, cells, results)
     del Z
     chosen = "mixed32" if "mixed32" in results else modes[0]
     r = results[chosen]
@@ -264,6 +331,9 @@ def main():
         out["config"]["max_dS_vs_fp64_plain"] = float(np.abs(r["S_sample"] - f64["S_sample"]).max())
         out["config"]["argmin_equal_fp64_plain"] = bool(r["am"] == f64["am"])
         out["config"]["fom_rel_dev_vs_fp64_plain"] = float(np.max(np.abs(r["fom"] - f64["fom"]) / f64["fom"]))
+    out["parent_fill"] = parent_fill
+    if lowrank is not None:
+        out["lowrank"] = lowrank
     if not args.no_cpu_baseline:
         sample_c = r["sample_c"]
         S_full = np.zeros((C,) + r["S_sample"].shape[1:], np.complex128)

@@ -109,6 +109,17 @@ int pxd_problem_classification(const pxd_problem* p, uint8_t* kind, int32_t* cel
  * mirrored.  Z_out: F x M x M complex128, row-major, caller-owned (host).
  * n_threads <= 0 uses every hardware thread.  Host only; needs no GPU. */
 int pxd_problem_fill(const pxd_problem* p, int32_t F, const double* freqs_hz, double* Z_out, int32_t n_threads);
+/* The same fill on GPU `device` (Section II-A's parent fill, the paper's
+ * Phase 2, run on the GPU instead of host cores): one FP64 thread per
+ * (test triangle, source triangle, test point) builds the source integrals,
+ * one per (m, n >= m) assembles Z_mn and mirrors it.  Z_out: device pointer,
+ * F x M x M complex128, caller-owned; work is enqueued on `stream` (a
+ * hipStream_t, NULL = default) and finished when the call returns.  Allocates
+ * a temporary table of T x T x 256 bytes (T triangles) plus the geometry;
+ * PXD_ENOMEM if that fails.  Agrees with pxd_problem_fill up to the rounding
+ * of the device math library. */
+int pxd_problem_fill_device(const pxd_problem* p, int32_t device, void* stream, int32_t F, const double* freqs_hz,
+                            double* Z_out);
 
 /* ---------------------------------------------------------------- evaluator */
 
@@ -156,6 +167,9 @@ const char* pxd_last_error(const pxd_ctx* ctx); /* ctx may be NULL: thread-local
 /* Parent matrices: F x M x M complex128 row-major host array, frequencies in Hz.
  * The library keeps a device copy (and a complex64 copy in the mixed modes). */
 int pxd_load_parent(pxd_ctx* ctx, int32_t M, int32_t F, const double* freqs_hz, const double* Z);
+/* Same, with the parent filled on the context's device by
+ * pxd_problem_fill_device straight into the context's copy (no host matrix). */
+int pxd_load_parent_problem(pxd_ctx* ctx, const pxd_problem* p, int32_t F, const double* freqs_hz);
 
 /* Pixel-to-RWG map (Section II-C): per parent function its kind and the cells
  * it needs (cell_b = -1 if one); P ports with their parent function index

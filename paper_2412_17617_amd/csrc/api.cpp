@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "problem.hpp"
 #include "pxd.h"
 #include "status.hpp"
 #include "surrogate.hpp"
@@ -527,6 +528,41 @@ int pxd_load_parent(pxd_ctx* ctx, int32_t M, int32_t F, const double* freqs_hz, 
   ++ctx->gen;
   ctx->terms.release();  // band ids depend on the frequency grid
   ctx->n_terms = 0;
+  return PXD_OK;
+}
+
+int pxd_load_parent_problem(pxd_ctx* ctx, const pxd_problem* p, int32_t F, const double* freqs_hz) {
+  if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  if (!p || F <= 0 || !freqs_hz) return ctx->fail(PXD_EINVAL, "invalid parent arguments");
+  const int M = (int)p->p.rwg.size();
+  if (ctx->cell_a.p && M != ctx->M) return ctx->fail(PXD_ESHAPE, "parent size differs from the loaded map");
+  HIPCHK(ctx, hipSetDevice(ctx->opt.device));
+  const size_t n = (size_t)F * M * M;
+  ctx->Z128.release();
+  ctx->Z64.release();
+  HIPCHK(ctx, ctx->Z128.ensure(n * 16));
+  std::string err;
+  int rc;
+  try {
+    rc = pxd::fill_problem_device(p->p, F, freqs_hz, ctx->Z128.as<double>(), ctx->stream, &err);
+  } catch (const std::bad_alloc&) {
+    rc = PXD_ENOMEM, err = "out of host memory";
+  }
+  if (rc != PXD_OK) {
+    ctx->Z128.release();
+    return ctx->fail(rc, err);
+  }
+  if (ctx->opt.precision != PXD_PREC_FP64) {
+    HIPCHK(ctx, ctx->Z64.ensure(n * 8));
+    HIPCHK(ctx, pxd::launch_to_c64(ctx->stream, ctx->Z128.as<double2>(), ctx->Z64.as<float2>(), n));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->M = M;
+  ctx->F = F;
+  ctx->freqs.assign(freqs_hz, freqs_hz + F);
+  ctx->terms.release();
+  ctx->n_terms = 0;
+  ++ctx->gen;
   return PXD_OK;
 }
 

@@ -1,4 +1,6 @@
-// C ABI for the host-side structure builder and parent fill.
+// C ABI for the structure builder and the parent fill (host and device).
+#include <hip/hip_runtime.h>
+
 #include <cstring>
 #include <new>
 #include <string>
@@ -6,10 +8,6 @@
 #include "problem.hpp"
 #include "pxd.h"
 #include "status.hpp"
-
-struct pxd_problem {
-  pxd::Problem p;
-};
 
 extern "C" {
 
@@ -70,6 +68,22 @@ int pxd_problem_fill(const pxd_problem* p, int32_t F, const double* freqs_hz, do
   int rc;
   try {
     rc = pxd::fill_problem(p->p, F, freqs_hz, Z_out, n_threads, &err);
+  } catch (const std::bad_alloc&) {
+    rc = PXD_ENOMEM, err = "out of host memory";
+  }
+  if (rc != PXD_OK) return pxd::set_thread_error(rc, err);
+  return PXD_OK;
+}
+
+int pxd_problem_fill_device(const pxd_problem* p, int32_t device, void* stream, int32_t F, const double* freqs_hz,
+                            double* Z_out) {
+  if (!p) return pxd::set_thread_error(PXD_EINVAL, "problem is NULL");
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return pxd::set_thread_error(PXD_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  std::string err;
+  int rc;
+  try {
+    rc = pxd::fill_problem_device(p->p, F, freqs_hz, Z_out, stream, &err);
   } catch (const std::bad_alloc&) {
     rc = PXD_ENOMEM, err = "out of host memory";
   }

@@ -55,5 +55,12 @@ struct Problem {
 
 int build_problem(const pxd_geometry* g, Problem* out, std::string* err);
 int fill_problem(const Problem& p, int F, const double* freqs, double* Z, int n_threads, std::string* err);
+// The same fill on the current device: Zdev is a device pointer (F x M x M
+// complex128), work enqueued on `stream` (a hipStream_t) and finished on return.
+int fill_problem_device(const Problem& p, int F, const double* freqs, double* Zdev, void* stream, std::string* err);
 
 }  // namespace pxd
+
+struct pxd_problem {
+  pxd::Problem p;
+};

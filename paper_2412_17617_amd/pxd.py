@@ -72,6 +72,8 @@ _SIGS = {
     "pxd_problem_sizes": (C.c_int, [_VP, _VP, _VP, _VP]),
     "pxd_problem_classification": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pxd_problem_fill": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32]),
+    "pxd_problem_fill_device": (C.c_int, [_VP, C.c_int32, _VP, C.c_int32, _VP, _VP]),
+    "pxd_load_parent_problem": (C.c_int, [_VP, _VP, C.c_int32, _VP]),
     "pxd_create": (C.c_int, [C.POINTER(Options), C.POINTER(_VP)]),
     "pxd_destroy": (None, [_VP]),
     "pxd_last_error": (C.c_char_p, [_VP]),
@@ -180,6 +182,16 @@ class Problem:
         _check(lib().pxd_problem_fill(self._h, len(freqs), _ptr(freqs), _ptr(Z), n_threads))
         return Z
 
+    def fill_device(self, freqs, out, stream=None, device=0):
+        """Fill on the GPU into `out`: a device buffer of F x M x M complex128
+        (a torch CUDA tensor, complex128 or float64 with a trailing 2, or any
+        object with data_ptr()).  Returns when the fill is finished."""
+        freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+        sp = getattr(stream, "cuda_stream", stream)
+        _check(lib().pxd_problem_fill_device(self._h, device, _VP(sp) if sp else None, len(freqs), _ptr(freqs),
+                                             _VP(out.data_ptr())))
+        return out
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib_handle is not None:
             _lib_handle.pxd_problem_destroy(self._h)
@@ -207,6 +219,12 @@ class Evaluator:
         assert M == M2 and F == len(freqs)
         self._c(lib().pxd_load_parent(self._h, M, F, _ptr(freqs), _ptr(Z)))
         self.M, self.F = M, F
+
+    def load_parent_problem(self, problem, freqs):
+        """Parent filled on this context's GPU from the structure (no host matrix)."""
+        freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+        self._c(lib().pxd_load_parent_problem(self._h, problem._h, len(freqs), _ptr(freqs)))
+        self.M, self.F = problem.M, len(freqs)
 
     def load_map(self, n_cells, kind, cell_a, cell_b, port_bf, port_len, z0=50.0):
         kind = np.ascontiguousarray(kind, np.uint8)
