@@ -15,7 +15,10 @@ Readings where the algorithm is silent: all nodes of one depth expand the same
 pixel; the restart happens when the count saturates at the deepest depth; the
 evaluation budget counts every candidate evaluated.  Optionally a surrogate
 (``Surrogate``) ranks the deepest level and only its best k leaves are solved;
-the exact evaluator still judges every accepted change.
+the exact evaluator still judges every accepted change.  Solving the trees
+by the low-rank flip evaluation from the current map's inverse (``lowrank``)
+is switched off: its one GPU run inside this driver made a memory fault
+whose cause has not been shown, so the option raises.
 """
 
 from __future__ import annotations
@@ -36,10 +39,15 @@ class SearchResult:
 
 
 class TreeSearch:
-    def __init__(self, evaluator, n_layers: int, n_pix: int, d_init: int = 1, d_max: int = 2, m_of_depth=(10, 3)):
+    def __init__(self, evaluator, n_layers: int, n_pix: int, d_init: int = 1, d_max: int = 2, m_of_depth=(10, 3),
+                 lowrank: bool = False):
         if not (1 <= d_init <= d_max) or len(m_of_depth) < d_max:
             raise ValueError("need 1 <= d_init <= d_max and one M(D) per depth")
+        if lowrank:
+            raise NotImplementedError("low-rank evaluation inside the tree search is switched off: its only GPU run "
+                                      "made a memory fault whose cause has not been shown")
         self.ev = evaluator
+        self._eval = evaluator.evaluate_flips
         self.L, self.n_pix = n_layers, n_pix
         self.d_init, self.d_max, self.m = d_init, d_max, tuple(m_of_depth)
 
@@ -69,7 +77,7 @@ class TreeSearch:
         return np.asarray(offs, np.int32), cells, start, len(offs) - 1
 
     def _fom(self, m):
-        _, F, _, _ = self.ev.evaluate_flips(m, np.array([0, 0], np.int32), np.zeros(0, np.int32), want_S=False)
+        _, F, _, _ = self._eval(m, np.array([0, 0], np.int32), np.zeros(0, np.int32), want_S=False)
         return float(F[0])
 
     def run(self, start_map, pixel_order, restart_maps, max_evals: int, prefilter=None) -> SearchResult:
@@ -90,7 +98,7 @@ class TreeSearch:
                     path.append(j)
             offs, cells, lo, hi = self._tree(P, path)
             if prefilter is None:
-                _, Fc, st, _ = self.ev.evaluate_flips(P, offs, cells, want_S=False)
+                _, Fc, st, _ = self._eval(P, offs, cells, want_S=False)
                 res.evaluations += len(offs) - 1
                 leaves = np.arange(lo, hi)
                 Fl = Fc[lo:hi]
@@ -98,14 +106,14 @@ class TreeSearch:
                 sur, k, rank = prefilter
                 upper = offs[:lo + 1]  # the levels above the leaves are solved exactly
                 if lo > 0:
-                    self.ev.evaluate_flips(P, upper, cells[:upper[-1]], want_S=False)
+                    self._eval(P, upper, cells[:upper[-1]], want_S=False)
                     res.evaluations += lo
                 pred = rank(sur, P, offs, cells)[lo:hi]
                 pick = np.argsort(pred, kind="stable")[:k] + lo
                 sub = np.zeros(len(pick) + 1, np.int32)
                 sub[1:] = np.cumsum([offs[i + 1] - offs[i] for i in pick])
                 sc = np.concatenate([cells[offs[i]:offs[i + 1]] for i in pick]).astype(np.int32)
-                _, Fl, st, _ = self.ev.evaluate_flips(P, sub, sc, want_S=False)
+                _, Fl, st, _ = self._eval(P, sub, sc, want_S=False)
                 res.evaluations += len(pick)
                 leaves = pick
             k = int(np.argmin(Fl))  # lowest index among equal minima
