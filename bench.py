@@ -41,10 +41,10 @@ def lu_flops(N, P):
 KERNEL_OF = {"fp64": "k_eval_plain", "mixed32": "k_eval_mixed"}
 
 
-def measured_traffic(workload, mode, items):
-    """HBM bytes per launch of the evaluator kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
-    none for this workload or the kernel sources changed since it was taken."""
+def measured_traffic(workload, kernel, items):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is none for
+    this workload or the kernel sources changed since it was taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"k_eval_{workload}_traffic.json")
@@ -56,7 +56,7 @@ def measured_traffic(workload, mode, items):
     for f in rec["source_files"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    k = rec["kernels"].get(KERNEL_OF[mode])
+    k = rec["kernels"].get(kernel)
     if h.hexdigest() != rec["source_sha256"] or k is None or rec["items_per_launch"] != items:
         return None
     return k["hbm_bytes_per_launch"]
@@ -149,6 +149,7 @@ def lowrank_leg(args, pxd, spec, pb, Z, base, off, cells, results):
         "io": "host buffers (PCIe copies of flips and S inside the timed step)",
         "g_stream": {"bytes_per_launch": g_bytes, "achieved_GBps": g_bytes / (k / 1e3) / 1e9,
                      "basis": "N_B^2 x 16 B per pass, ceil(added / 4) passes per (candidate, frequency)"},
+        "traffic": measured_traffic(spec.name, "k_lowrank", C * spec.n_freq),
     }
     if "fp64" in results:
         f64 = results["fp64"]
@@ -317,7 +318,7 @@ def main():
             "kernel_ms": r["kernel_ms"],
         },
     }
-    traffic = measured_traffic(spec.name, chosen, C * spec.n_freq)
+    traffic = measured_traffic(spec.name, KERNEL_OF[chosen], C * spec.n_freq)
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
         out["roofline"]["traffic_unit"] = "bytes/launch"
@@ -326,7 +327,7 @@ def main():
         f64 = results["fp64"]
         out["fp64_plain"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"], "kernel_ms": f64["kernel_ms"],
                              "roofline_frac": f64["achieved"] / f64["peak"], "achieved_tflops": f64["achieved"],
-                             "traffic": measured_traffic(spec.name, "fp64", C * spec.n_freq)}
+                             "traffic": measured_traffic(spec.name, KERNEL_OF["fp64"], C * spec.n_freq)}
         out["speedup_vs_fp64_plain"] = r["value"] / f64["value"]
         out["config"]["max_dS_vs_fp64_plain"] = float(np.abs(r["S_sample"] - f64["S_sample"]).max())
         out["config"]["argmin_equal_fp64_plain"] = bool(r["am"] == f64["am"])
