@@ -161,6 +161,55 @@ def lowrank_leg(args, pxd, spec, pb, Z, base, off, cells, results):
     return out
 
 
+def surrogate_leg(args, pxd, spec, pb, torch):
+    """Ranking by the CNN surrogate at its working size: a 3 x 24 x 24 map
+    (channels 32-64, hidden 256, BF16 products) scored on the workload's 101
+    frequencies with its FoM table; every single flip and every pair of
+    cells, then the top 32.  Random-init weights (throughput only)."""
+    dev = torch.device("cuda:0")
+    ev = pxd.Evaluator(device=0)
+    ev.load_problem(pb, spec.z0)
+    ev.load_parent_problem(pb, spec.freqs)
+    ev.set_fom_paper()
+    L, ny, nx = 3, 24, 24
+    n = L * ny * nx
+    sur = pxd.Surrogate(L, ny, nx, spec.freqs, spec.freqs[0], spec.freqs[-1], precision=pxd.SUR_BF16,
+                        max_batch=2048)
+    sur.init_params(17)
+    iu, ju = np.triu_indices(n, 1)
+    C = n + len(iu)
+    off = np.concatenate([np.arange(n + 1), n + 2 * np.arange(1, len(iu) + 1)]).astype(np.int32)
+    cells = np.concatenate([np.arange(n), np.stack([iu, ju], 1).ravel()]).astype(np.int32)
+    base = (np.arange(n) % 2).astype(np.uint8)
+    t_base, t_off, t_cells = (torch.from_numpy(a).to(dev) for a in (base, off, cells))
+    fp = torch.empty(C, dtype=torch.float64, device=dev)
+    top = torch.empty(32, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    sur.rank(ev, t_base, t_off, t_cells, 32, fp, top, stream)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sur.rank(ev, t_base, t_off, t_cells, 32, fp, top, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ok = bool(torch.isfinite(fp).all().item()) and int(top.min().item()) >= 0
+    log(f"[surrogate] ranked {C:,} candidates (3x24x24 map, 101 frequencies) in {ms:.0f} ms, top-32 valid {ok}")
+    # trunk work per map: four 3x3 convolutions; head: two products per (map, frequency)
+    ch = (3, 32, 32, 64, 64)
+    px = (ny * nx, ny * nx, ny * nx // 4, ny * nx // 4)
+    trunk = sum(2 * 9 * ch[i] * ch[i + 1] * px[i] for i in range(4))
+    feat = 64 * (ny // 4) * (nx // 4)
+    flops = C * (trunk + 2 * feat * 256 + len(spec.freqs) * 2 * 256 * 9)
+    sur.close()
+    ev.close()
+    return {"value": C / (ms / 1e3), "unit": "maps/s", "ms": ms, "candidates": C,
+            "workload": "every single flip and cell pair of a 3x24x24 map, 101 frequencies, top 32",
+            "precision": "bf16 products, fp32 accumulation", "weights": "random init (throughput only)",
+            "flops_per_call": flops, "achieved_TFLOPs": flops / (ms / 1e3) / 1e12, "peak_TFLOPs": 2500.0,
+            "top_valid": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +220,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank flip evaluation leg")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate ranking leg")
     ap.add_argument("--fill-threads", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device, a reference kernel of known traffic for "
@@ -279,6 +329,7 @@ def main():
         ev.close()
         del S_out
     lowrank = None if args.no_lowrank else lowrank_leg(args, pxd, spec, pb, Z, base, off, cells, results)
+    surrogate = None if args.no_surrogate else surrogate_leg(args, pxd, spec, pb, torch)
     del Z
     chosen = "mixed32" if "mixed32" in results else modes[0]
     r = results[chosen]
@@ -335,6 +386,8 @@ def main():
     out["parent_fill"] = parent_fill
     if lowrank is not None:
         out["lowrank"] = lowrank
+    if surrogate is not None:
+        out["surrogate"] = surrogate
     if not args.no_cpu_baseline:
         sample_c = r["sample_c"]
         S_full = np.zeros((C,) + r["S_sample"].shape[1:], np.complex128)

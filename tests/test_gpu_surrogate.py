@@ -70,6 +70,25 @@ def test_forward_matches_oracle(prec):
 
 
 @pytest.mark.parametrize("prec", [pxd.SUR_FP32, pxd.SUR_BF16])
+def test_forward_at_full_size_matches_oracle(prec):
+    """The ranking network at its working size: 3 x 24 x 24 maps, channels
+    32-64, hidden 256, 101 frequencies, buffers for 2,048 maps per call."""
+    cfg = osur.SurrogateConfig(n_layers=3, ny=24, nx=24, channels=(32, 32, 64, 64), hidden=256, emb=16, n_out=9)
+    freqs = np.linspace(1e9, 8e9, 101)
+    s = make(prec, max_batch=2048, cfg=cfg, freqs=freqs)
+    p32 = init_params(cfg, 12).astype(np.float32)
+    s.set_params(p32)
+    maps = random_maps(3, 3 * 24 * 24, 13)
+    out = torch.zeros((3, len(freqs), 9), dtype=torch.float32, device=DEV)
+    s.forward(torch.from_numpy(maps).to(DEV), out)
+    got = out.cpu().numpy()
+    want, _ = osur.forward(p32.astype(np.float64), maps, u_of(freqs), cfg)
+    print(f"full-size forward relative error {rel(got, want):.2e}")
+    assert rel(got, want) <= (1e-4 if prec == pxd.SUR_FP32 else 2e-2), rel(got, want)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [pxd.SUR_FP32, pxd.SUR_BF16])
 def test_gradient_matches_oracle(prec):
     s = make(prec)
     p32 = init_params(CFG, 5).astype(np.float32)
