@@ -6,6 +6,8 @@
 // done in a fixed order, so results are reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -32,10 +34,26 @@ __device__ __forceinline__ short to_bf16(float f) {
   return (short)(u >> 16);
 }
 
+// Problems whose A operand is cheaper with a per-row context computed once
+// per tile (Prob::Row, row(m), a_row(row, k)) instead of a(m, k) per element.
+template <typename Prob, typename = void>
+struct HasRows {
+  static constexpr bool value = false;
+};
+template <typename Prob>
+struct HasRows<Prob, std::void_t<typename Prob::Row>> {
+  static constexpr bool value = true;
+};
+struct Dummy {  // row type of the problems without a row context
+  struct Row {};
+};
+
 // C = A B over a 64 x 64 output tile per workgroup (four waves of 32 x 32,
 // each 2 x 2 MFMA tiles).  Prob supplies M, N, K, a(m, k), b(k, n) and
 // store(m, n, value, split); blockIdx.z selects a slice of K (split-K, the
-// caller reduces the slices).
+// caller reduces the slices).  Each thread stages the same column kk of A for
+// the rows r = tid / TK + (256 / TK) i, so a problem with a row context
+// decodes its rows once per tile.
 template <typename Prob, bool BF16>
 __global__ __launch_bounds__(256) void k_gemm(Prob pr, int k_per_split) {
   __shared__ float As[TM][TK + 1];
@@ -50,12 +68,31 @@ __global__ __launch_bounds__(256) void k_gemm(Prob pr, int k_per_split) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
-  for (int k0 = kb; k0 < ke; k0 += TK) {
+  constexpr int RPT = TM * TK / 256;  // A elements staged per thread
+  constexpr int RSTEP = 256 / TK;     // row stride between them
+  static_assert(TM * TK % 256 == 0 && 256 % TK == 0, "staging layout");
+  const int kk_a = tid % TK, r_a = tid / TK;
+  [[maybe_unused]] typename std::conditional<HasRows<Prob>::value, Prob, Dummy>::type::Row rows[RPT];
+  if constexpr (HasRows<Prob>::value) {
 #pragma unroll
-    for (int e = tid; e < TM * TK; e += 256) {
-      const int r = e / TK, kk = e - r * TK;
-      const int m = m0 + r, k = k0 + kk;
-      As[r][kk] = (m < pr.M && k < ke) ? pr.a(m, k) : 0.0f;
+    for (int i = 0; i < RPT; ++i) rows[i] = pr.row(m0 + r_a + RSTEP * i);
+  }
+  for (int k0 = kb; k0 < ke; k0 += TK) {
+    if constexpr (HasRows<Prob>::value) {
+      const int k = k0 + kk_a;
+      const auto kc = pr.col(k < ke ? k : 0);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = r_a + RSTEP * i;
+        As[r][kk_a] = (m0 + r < pr.M && k < ke) ? pr.a_row(rows[i], kc) : 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int e = tid; e < TM * TK; e += 256) {
+        const int r = e / TK, kk = e - r * TK;
+        const int m = m0 + r, k = k0 + kk;
+        As[r][kk] = (m < pr.M && k < ke) ? pr.a(m, k) : 0.0f;
+      }
     }
 #pragma unroll
     for (int e = tid; e < TK * TN; e += 256) {
@@ -111,6 +148,7 @@ struct Img {
   int B, H, W, C;
 };
 
+
 // Input of the first conv: the map bytes themselves.
 struct MapSrc {
   const uint8_t* maps;
@@ -140,6 +178,26 @@ struct ConvFwd {
     const int x = m % g.W, t = m / g.W, y = t % g.H, b = t / g.H;
     const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
     return (yy >= 0 && yy < g.H && xx >= 0 && xx < g.W) ? src.at(b, yy, xx, ci, g) : 0.0f;
+  }
+  // row context: the pixel (b, y, x) of output row m (rows past M decode to
+  // pixels that a_row never reads: the caller masks them)
+  struct Row {
+    int b, y, x;
+  };
+  struct Col {
+    int dy, dx, ci;
+  };
+  __device__ Row row(int m) const {
+    const int x = m % g.W, t = m / g.W;
+    return Row{t / g.H, t % g.H, x};
+  }
+  __device__ Col col(int k) const {
+    const int tap = k / g.C;
+    return Col{tap / 3 - 1, tap % 3 - 1, k - tap * g.C};
+  }
+  __device__ float a_row(const Row& r, const Col& c) const {
+    const int yy = r.y + c.dy, xx = r.x + c.dx;
+    return (yy >= 0 && yy < g.H && xx >= 0 && xx < g.W) ? src.at(r.b, yy, xx, c.ci, g) : 0.0f;
   }
   __device__ float b(int k, int n) const { return w[(size_t)k * N + n]; }
   __device__ void store(int m, int n, float v, int) const { z[(size_t)m * N + n] = v + bias[n]; }
@@ -361,10 +419,13 @@ __global__ void k_candidate_maps(const uint8_t* base, const int* off, const int*
 // predicted are skipped.  pred: n x F x (3 n_entries), per entry ln|S| first.
 __global__ void k_pred_fom(const float* pred, int n, int F, int n_ent, const int* ent_i, const int* ent_j,
                            FomTable t, double* fom) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  // one wave per map: lanes take the frequencies in turn, then a fixed-order
+  // wave reduction
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (r >= n) return;  // whole waves leave together
   double acc = 0.0;
-  for (int f = 0; f < F; ++f) {
+  for (int f = lane; f < F; f += 64) {
     const int bnd = t.band[f];
     if (bnd < 0) continue;
     for (int q = 0; q < t.n_terms; ++q) {
@@ -378,7 +439,9 @@ __global__ void k_pred_fom(const float* pred, int n, int F, int n_ent, const int
       acc += t.term_fac[q] * pow(m2, 0.5 * t.terms[q].power);
     }
   }
-  fom[r] = acc;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) fom[r] = acc;
 }
 
 // k smallest (value, index) pairs in increasing order; pass j takes the least
@@ -848,7 +911,7 @@ int pxd_sur_rank(pxd_sur* s, const pxd_ctx* ctx, void* stream, const uint8_t* ba
     SURCHK(s, hipGetLastError());
     if (int rc = forward(s, st, n, s->maps.as<uint8_t>())) return rc;
     const int* ei = s->ent.as<int>();
-    hipLaunchKernelGGL(k_pred_fom, dim3((n + 255) / 256), dim3(256), 0, st, s->out.as<float>(), n, s->F,
+    hipLaunchKernelGGL(k_pred_fom, dim3((n + 3) / 4), dim3(256), 0, st, s->out.as<float>(), n, s->F,
                        s->cfg.n_entries, ei, ei + 4, t, fom_pred + c0);
     SURCHK(s, hipGetLastError());
   }
