@@ -278,10 +278,15 @@ def main():
     results = {}
     for mode in modes:
         prec = pxd.PREC_FP64 if mode == "fp64" else pxd.PREC_MIXED32
-        ev = pxd.Evaluator(device=0, precision=prec)
+        # full-width register sub-panel; workgroups per CU and item order autotuned
+        ev = pxd.Evaluator(device=0, precision=prec, half_subpanel=1)
         ev.load_parent(Z, freqs)
         ev.load_problem(pb, spec.z0)
         ev.set_fom_paper()
+        n_tune = min(C, 96)
+        tune = ev.autotune(base, off[:n_tune + 1], cells[:off[n_tune]], n_reps=1)
+        log(f"[{mode}] autotuned on {n_tune} candidates: " +
+            ", ".join(f"wg/CU {t['wg_per_cu']} order {t['schedule']} {t['ms']:.0f} ms" for t in tune))
         S_out = torch.empty((C, spec.n_freq, P, P, 2), dtype=torch.float64, device=dev)
         fom_out = torch.empty(C, dtype=torch.float64, device=dev)
         st_out = torch.empty(C, dtype=torch.int32, device=dev)
@@ -321,6 +326,9 @@ def main():
             "ir_steps": int(stats[-1]["ir_iterations"]), "status_nonzero": int(np.count_nonzero(
                 (st_out.cpu().numpy() != 0) & (st_out.cpu().numpy() != 1))),
             "fom": fom_out.cpu().numpy(), "am": int(am_out.cpu().numpy()[0]),
+            "tuned": {"wg_per_cu": tune[0]["wg_per_cu"], "schedule": tune[0]["schedule"], "half_subpanel": 1,
+                      "tried": [(t["wg_per_cu"], t["schedule"], round(t["ms"], 1)) for t in tune],
+                      "batch": f"first {n_tune} candidates"},
             "S_sample": None,
         }
         sample_c = list(range(0, C, max(1, C // 16)))[:16]
@@ -357,6 +365,7 @@ def main():
             "status_errors": r["status_nonzero"],
             "fallback_items": r["fallbacks"],
             "refinement_steps": r["ir_steps"],
+            "launch": r["tuned"],
         },
         "roofline": {
             "bound": "mfma",

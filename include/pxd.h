@@ -258,7 +258,8 @@ typedef struct pxd_tune_entry {
 /* Time every configuration (workgroups per CU x sub-panel width x item order)
  * on this batch (host buffers, as pxd_evaluate_flips), n_reps times each, and
  * keep the fastest for the batch's precision and size class; later calls
- * whose options say "tuned" use it.  report (may be NULL) receives up to
+ * whose options say "tuned" use it.  A choice the context's options fix
+ * (wg_per_cu > 0, half_subpanel 1 or 2, schedule not AUTO) is not searched.  report (may be NULL) receives up to
  * max_report entries, *n_report the number written; the chosen one is
  * report[0]. */
 int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,

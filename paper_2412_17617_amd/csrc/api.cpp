@@ -738,9 +738,17 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
   n_reps = std::max(1, n_reps);
   std::vector<pxd_tune_entry> tried;
   int Q = 0;
-  for (int wg = 2; wg >= 1; --wg)
-    for (int half = 0; half <= 1; ++half)
-      for (int sched = PXD_SCHED_FREQ_MAJOR; sched <= PXD_SCHED_SIZE_MAJOR; ++sched) {
+  // options the context fixes explicitly are not searched
+  const int wg_hi = ctx->opt.wg_per_cu > 0 ? std::min(ctx->opt.wg_per_cu, 2) : 2;
+  const int wg_lo = ctx->opt.wg_per_cu > 0 ? wg_hi : 1;
+  const bool half_fixed = ctx->opt.half_subpanel == 1 || ctx->opt.half_subpanel == 2;
+  const int half_lo = half_fixed ? ctx->opt.half_subpanel - 1 : 0, half_hi = half_fixed ? half_lo : 1;
+  const bool sched_fixed = ctx->opt.schedule != PXD_SCHED_AUTO;
+  const int sched_lo = sched_fixed ? ctx->opt.schedule : PXD_SCHED_FREQ_MAJOR;
+  const int sched_hi = sched_fixed ? ctx->opt.schedule : PXD_SCHED_SIZE_MAJOR;
+  for (int wg = wg_hi; wg >= wg_lo; --wg)
+    for (int half = half_lo; half <= half_hi; ++half)
+      for (int sched = sched_lo; sched <= sched_hi; ++sched) {
         Tuning t;
         t.wg_per_cu = wg, t.half_sb = half, t.schedule = sched, t.valid = true;
         double best = 1e300;

@@ -104,6 +104,24 @@ def test_autotune_picks_a_measured_configuration(tmp_path):
     ev2.close()
 
 
+def test_autotune_keeps_fixed_options():
+    """Choices fixed by the options are not searched: with the full-width
+    sub-panel and the frequency-major order fixed only the two workgroup
+    counts are tried, and the tuned context still matches the oracle."""
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_FP64, half_subpanel=1, schedule=pxd.SCHED_FREQ_MAJOR)
+    rep = ev.autotune(base, off, cells)
+    assert sorted(r["wg_per_cu"] for r in rep) == [1, 2]
+    assert all(r["half_subpanel"] == 0 and r["schedule"] == pxd.SCHED_FREQ_MAJOR for r in rep)
+    S, F, status, am = ev.evaluate_flips(base, off, cells)
+    S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
+    check(S, F, S_o, F_o, pxd.PREC_FP64)
+    ev.close()
+
+
 @pytest.mark.parametrize("prec", [pxd.PREC_FP64, pxd.PREC_MIXED32])
 def test_graph_replays_follow_inputs(prec):
     """Capture once, replay several times; between replays the caller edits
