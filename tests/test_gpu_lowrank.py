@@ -68,10 +68,12 @@ def test_single_flips_match_oracle(name):
     assert am == order[0] or abs(F_o[am] - F_o[order[0]]) <= FOM_RTOL * F_o[order[0]]
 
 
-def test_multi_flips_empty_and_fallback():
+@pytest.mark.parametrize("prec", [pxd.PREC_FP64, pxd.PREC_MIXED32])
+def test_multi_flips_empty_and_fallback(prec):
     """No flips (the base map itself), pairs and triples, a flip that toggles
     back, and candidates far from the base that exceed the low-rank limits
-    and go to the dense FP64 kernel in the same call."""
+    and go to the dense FP64 kernel in the same call (also from a context
+    whose own dense path is the mixed one: the low-rank call stays FP64)."""
     spec = get_spec("small6x3")
     st, Z, freqs = oracle_parent(spec, (0, 2, 4))
     n = spec.n_cells
@@ -83,7 +85,7 @@ def test_multi_flips_empty_and_fallback():
     S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
     over = over_limit(st, base, off, cells)
     assert over.any() and not over.all()
-    ev, _ = make_evaluator(spec, Z, freqs)
+    ev, _ = make_evaluator(spec, Z, freqs, precision=prec)
     S, F, status, am = ev.evaluate_flips_lowrank(base, off, cells)
     stats = ev.stats()
     ev.close()
