@@ -1337,11 +1337,26 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
         const double rho = (iters == 1) ? 1.0 : (s_mprev > 0.0 ? m / s_mprev : 0.0);
         const double left = m * rho / (1.0 - rho);
         bool ok = rho < 0.9;
-        for (int q = 0; q < P * P && ok; ++q) ok = left <= p.ir_tol * s_sabs[q] + kIrAbsFloor;
-        s_conv = ok ? 1 : 0;
+        double target = 1e300;
+        for (int q = 0; q < P * P; ++q) target = fmin(target, p.ir_tol * s_sabs[q] + kIrAbsFloor);
+        ok = ok && left <= target;
+        int verdict = ok ? 1 : 0;
+        if (!ok && iters >= 3) {
+          // give up early when the observed contraction cannot reach the
+          // target within the remaining steps (the FP64 path takes the item):
+          // after k more steps the estimate is left rho^k
+          if (!(rho < 1.0) || !(left == left)) {
+            verdict = 2;
+          } else if (rho > 0.0 && left > 0.0) {
+            const double k_needed = log(target / left) / log(rho);
+            if (iters + k_needed > (double)p.ir_max) verdict = 2;
+          }
+        }
+        s_conv = verdict;
       }
       __syncthreads();
-      conv = s_conv != 0;
+      conv = s_conv == 1;
+      if (s_conv == 2) break;
       if (conv) {  // converged: the port corrections finish the step
         if (tid < P * P) {
           double2* xv = x + (size_t)(N - P + tid / P) * P + tid % P;
