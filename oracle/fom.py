@@ -15,8 +15,10 @@ Readings (the paper leaves these open):
 * A term whose S entry does not exist (fewer than three ports) is dropped.
 * |S| is clamped below at 1e-15 (|S|^2 >= 1e-30) so that 1/rw_p stays finite.
 
-Parity: pinned by every term equalling exactly 1 at its threshold, by a hand
-computed value, and by band counts on the workload grids
+Parity: pinned by every term equalling exactly 1 at its threshold, by every
+term's value at two levels off all thresholds (tests/golden/fom_slopes.json,
+written out from the exponents, which fixes each slope), by the variant
+tables summed from those values, and by band counts on the workload grids
 (tests/test_oracle_fom.py).
 """
 

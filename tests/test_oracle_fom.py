@@ -80,18 +80,52 @@ def test_clamp_keeps_fom_finite():
     assert np.isfinite(fom.fom(S, f))
 
 
-def test_variant_tables_differ_from_eq8_by_exactly_their_terms():
-    """Section III-D: 'rej' swaps rw_s1/rw_s2 for their -45 dB forms, 'iso'
-    adds the isolation term over both passbands."""
-    spec = get_spec("batched20")
-    freqs = spec.freqs
-    rng = np.random.default_rng(3)
-    S = (rng.standard_normal((len(freqs), 3, 3)) + 1j * rng.standard_normal((len(freqs), 3, 3))) * 0.2
-    p1, p2, fi, fs = fom.band_sets(freqs)
-    base = fom.fom(S, freqs)
-    rw = [fom.rewards(S[k]) for k in range(len(freqs))]
-    iso_extra = sum(1.0 / rw[k]["oiiso"] for k in range(len(freqs)) if p1[k] or p2[k])
-    assert abs(fom.fom(S, freqs, "iso") - (base + iso_extra)) <= 1e-12 * base
-    rej = base - sum(1.0 / rw[k]["s2"] - 1.0 / rw[k]["s2rej"] for k in range(len(freqs)) if p1[k]) \
-        - sum(1.0 / rw[k]["s1"] - 1.0 / rw[k]["s1rej"] for k in range(len(freqs)) if p2[k])
-    assert abs(fom.fom(S, freqs, "rej") - rej) <= 1e-12 * base
+SLOPES = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fom_slopes.json")))
+
+
+@pytest.mark.parametrize("term", list(SLOPES["terms"]))
+@pytest.mark.parametrize("level", ["0.5", "0.01"])
+def test_each_reward_off_its_threshold(term, level):
+    """Eq. 9 / Section III-D: 1/rw at two levels of its entry (|S| = 0.5 and
+    0.01, on no threshold), against values written out from the exponents
+    (tests/golden/fom_slopes.json).  A wrong denominator or offset in any
+    exponent moves at least one of the two."""
+    t = SLOPES["terms"][term]
+    i, j = t["entry"]
+    S = np.full((3, 3), 0.2 + 0j)
+    S[i - 1, j - 1] = float(level)
+    got = 1.0 / fom.rewards(S)[term]
+    want = t["inv_rw"][level]
+    assert abs(got - want) <= 1e-12 * want
+
+
+def _const_s(level_of_entry, P=3):
+    S = np.full((P, P), 0.2 + 0j)
+    for (i, j), v in level_of_entry.items():
+        S[i - 1, j - 1] = v
+    return S
+
+
+@pytest.mark.parametrize("variant", ["paper", "rej", "iso"])
+def test_variant_tables_from_golden_terms(variant):
+    """Eq. 8 and its Section III-D variants on an S that is the same at every
+    frequency: the FoM is each band's point count times the sum of that
+    band's golden 1/rw values.  The bands' terms (Eq. 8: p1 -> p1, m1, s2;
+    p2 -> p2, m2, s1; f_i -> oi; f_s -> s3, s4; 'rej' swaps s1, s2 for their
+    -45 dB forms; 'iso' adds the isolation term over p1 and p2) are typed in
+    here from the equations, not taken from the oracle's table."""
+    freqs = get_spec("batched20").freqs  # band counts (11, 10, 7, 44), pinned above
+    counts = {"p1": 11, "p2": 10, "i": 7, "s": 44}
+    lv = {(1, 1): 0.5, (2, 1): 0.01, (3, 1): 0.5, (3, 2): 0.01}
+    g = {k: SLOPES["terms"][k]["inv_rw"]["0.5" if lv[tuple(v["entry"])] == 0.5 else "0.01"]
+         for k, v in SLOPES["terms"].items()}
+    table = {
+        "paper": {"p1": ["p1", "m1", "s2"], "p2": ["p2", "m2", "s1"], "i": ["oi"], "s": ["s3", "s4"]},
+        "rej": {"p1": ["p1", "m1", "s2rej"], "p2": ["p2", "m2", "s1rej"], "i": ["oi"], "s": ["s3", "s4"]},
+        "iso": {"p1": ["p1", "m1", "s2", "oiiso"], "p2": ["p2", "m2", "s1", "oiiso"], "i": ["oi"],
+                "s": ["s3", "s4"]},
+    }[variant]
+    want = sum(counts[b] * sum(g[t] for t in ts) for b, ts in table.items())
+    S = np.tile(_const_s(lv), (len(freqs), 1, 1))
+    got = fom.fom(S, freqs, variant)
+    assert abs(got - want) <= 1e-12 * want
