@@ -56,7 +56,12 @@ extern "C" {
 #define PXD_STATUS_FALLBACK 1     /* mixed precision did not converge; FP64 result returned */
 #define PXD_STATUS_NONFINITE (-1) /* a non-finite value reached S */
 #define PXD_STATUS_SINGULAR (-2)  /* an exactly zero pivot was met */
-#define PXD_STATUS_SIZE (-3)      /* active size above the bound a captured graph was built for (or < P) */
+#define PXD_STATUS_SIZE (-3)      /* active size above the bound a captured graph was built for (or < P);
+                                     the item's S entries are NaN */
+/* A candidate whose worst item status is negative has no valid S at some
+ * frequency: its FoM is +inf and it is never the argmin (Algorithm 1 accepts
+ * only a strict improvement of a valid FoM).  The argmin is -1 when no
+ * candidate of the batch has a finite FoM. */
 
 /* Order in which the persistent workgroups take (candidate, frequency) items. */
 #define PXD_SCHED_AUTO 0       /* tuned value if the context has one, else frequency-major */
@@ -192,8 +197,10 @@ int pxd_set_fom_variant(pxd_ctx* ctx, int32_t variant);
 
 /* Evaluate candidates given as flips of a base map: candidate c toggles cells
  * cells[offsets[c] .. offsets[c+1]).  Outputs (host, caller-owned, any may be
- * NULL): S_out n_cand x F x P x P complex128; fom_out n_cand; status n_cand
- * (worst item status); argmin_out the lowest-index minimum-FoM candidate. */
+ * NULL): S_out n_cand x F x P x P complex128; fom_out n_cand (+inf for a
+ * candidate with a negative status); status n_cand (worst item status);
+ * argmin_out the lowest-index minimum-FoM candidate among those with a finite
+ * FoM, -1 if there is none (Algorithm 1's arg min over the evaluated leaves). */
 int pxd_evaluate_flips(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,
                        const int32_t* cells, double* S_out, double* fom_out, int32_t* status,
                        int32_t* argmin_out);
@@ -236,6 +243,18 @@ int pxd_expand(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int3
 int pxd_gather(pxd_ctx* ctx, int32_t f, int32_t N, const int32_t* idx, double* ZA_out);
 
 int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out);
+
+/* The verdict the mixed-precision kernels take after refinement step `iters`
+ * (1-based) of an item, exposed so that the rule can be checked on the host.
+ * m: the largest change of any S_ij (Eq. 6) the step makes; m_prev: that of
+ * the previous step (0 before the first); target: min over the entries of
+ * ir_tol |S_ij| + 1e-11.  With the observed contraction rho = m / m_prev (1 on
+ * the first step) the error left in every entry is bounded by
+ * m rho / (1 - rho).  Returns 1 (converged: that bound is below target and
+ * rho < 0.9), 2 (give up from the third step on: rho >= 1, a NaN, or more
+ * steps needed than ir_max allows; the item goes to the FP64 path) or 0 (take
+ * another step); PXD_EINVAL if iters or ir_max is below 1.  Needs no GPU. */
+int pxd_refine_verdict(int32_t iters, int32_t ir_max, double m, double m_prev, double target);
 
 /* Candidates given as whole maps (an uneven batch: any mix of active sizes in
  * one persistent launch): maps is n_maps x n_cells, row c = candidate c.

@@ -328,10 +328,15 @@ int evaluate_lowrank(pxd_ctx* ctx, const uint8_t* base_map, int C, const int32_t
   const bool reuse = ctx->lr_gen == ctx->gen && ctx->lr_G.p &&
                      ctx->lr_map.size() == (size_t)ctx->n_cells &&
                      std::memcmp(ctx->lr_map.data(), base_map, ctx->n_cells) == 0;
-  if (!reuse)  // the base map's own active set, as a one-map batch
+  if (!reuse) {  // the base map's own active set, as a one-map batch
+    // lr_IB / lr_NB are overwritten below: the cached inverse no longer
+    // matches them, whether or not this call gets as far as recomputing it
+    ctx->lr_gen = -1;
+    ctx->lr_map.clear();
     HIPCHK(ctx, pxd::launch_expand(s, ctx->base.as<uint8_t>(), ctx->n_cells, (size_t)ctx->n_cells, nullptr, nullptr,
                                    1, ctx->cell_a.as<int>(), ctx->cell_b.as<int>(), M, ctx->lr_NB.as<int>(),
                                    ctx->lr_IB.as<int>()));
+  }
   ctx->hNc.resize(C + 1);
   HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data(), b.Nc.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data() + C, ctx->lr_NB.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -343,7 +348,6 @@ int evaluate_lowrank(pxd_ctx* ctx, const uint8_t* base_map, int C, const int32_t
   if (nmax > 2048 || NB > 2048) return ctx->fail(PXD_ESHAPE, "active size above 2048 is not supported");
   HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
   if (!reuse) {
-    ctx->lr_gen = -1;  // invalid until the inverse below is enqueued
     HIPCHK(ctx, pxd::launch_positions(s, ctx->lr_IB.as<int>(), NB, M, ctx->lr_pos.as<int>()));
     HIPCHK(ctx, ctx->lr_G.ensure(sizeof(double2) * (size_t)F * NB * NB));
     const int ld = (2 * NB + 3) / 4 * 4;
@@ -940,6 +944,11 @@ int pxd_gather(pxd_ctx* ctx, int32_t f, int32_t N, const int32_t* idx, double* Z
   didx.release();
   dout.release();
   return rc;
+}
+
+int pxd_refine_verdict(int32_t iters, int32_t ir_max, double m, double m_prev, double target) {
+  if (iters < 1 || ir_max < 1) return pxd::set_thread_error(PXD_EINVAL, "iters and ir_max must be >= 1");
+  return pxd::refine_verdict(iters, ir_max, m, m_prev, target);
 }
 
 int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out) {

@@ -909,6 +909,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_plain(EvalParams p) {
     const int N = p.Nc[c];
     double2* Sout = p.S + ((size_t)c * p.F + f) * p.P * p.P;
     if (N > kThreads * Q || N > p.nmax || N < p.P) {  // outside the size the launch was built for
+      // no solve: S is marked not-a-number and the status makes the FoM +inf
+      if (tid < p.P * p.P) Sout[tid] = double2{__builtin_nan(""), __builtin_nan("")};
       if (tid == 0) p.status[(size_t)c * p.F + f] = PXD_STATUS_SIZE;
       continue;
     }
@@ -1295,6 +1297,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
     const int N = p.Nc[c];
     double2* Sout = p.S + ((size_t)c * p.F + f) * P * P;
     if (N > kThreads * Q || N > p.nmax || N < P) {
+      if (tid < P * P) Sout[tid] = double2{__builtin_nan(""), __builtin_nan("")};
       if (tid == 0) p.status[(size_t)c * p.F + f] = PXD_STATUS_SIZE;
       continue;
     }
@@ -1334,24 +1337,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_eval_mixed(EvalParams p) {
         }
         // the contraction acts on the whole error, so what is left in any
         // entry is bounded by rho times the largest change, not its own change
-        const double rho = (iters == 1) ? 1.0 : (s_mprev > 0.0 ? m / s_mprev : 0.0);
-        const double left = m * rho / (1.0 - rho);
-        bool ok = rho < 0.9;
         double target = 1e300;
         for (int q = 0; q < P * P; ++q) target = fmin(target, p.ir_tol * s_sabs[q] + kIrAbsFloor);
-        ok = ok && left <= target;
-        int verdict = ok ? 1 : 0;
-        if (!ok && iters >= 3) {
-          // give up early when the observed contraction cannot reach the
-          // target within the remaining steps (the FP64 path takes the item):
-          // after k more steps the estimate is left rho^k
-          if (!(rho < 1.0) || !(left == left)) {
-            verdict = 2;
-          } else if (rho > 0.0 && left > 0.0) {
-            const double k_needed = log(target / left) / log(rho);
-            if (iters + k_needed > (double)p.ir_max) verdict = 2;
-          }
-        }
+        const int verdict = refine_verdict(iters, p.ir_max, m, s_mprev, target);
         s_conv = verdict;
       }
       __syncthreads();
@@ -1437,7 +1425,10 @@ __global__ void k_fom(const double2* __restrict__ S, int C, int F, int P, const 
       acc += term_fac[t] * pow(m2, 0.5 * terms[t].power);
     }
   }
-  fom[c] = acc;
+  // a candidate with any failed item (singular, non-finite, outside the
+  // launch's size bound) has no valid S at that frequency: it can never be
+  // selected, so its FoM is +inf
+  fom[c] = (worst < 0) ? __builtin_inf() : acc;
   if (cand_status) cand_status[c] = worst;
 }
 
@@ -1448,8 +1439,8 @@ __global__ void k_argmin(const double* __restrict__ fom, int C, int* __restrict_
   double best = __builtin_inf();
   int bi = 0x7fffffff;
   for (int c = tid; c < C; c += 256) {
-    double v = fom[c];
-    if (v != v) v = __builtin_inf();
+    const double v = fom[c];
+    if (!(v < __builtin_inf())) continue;  // +inf (failed candidate) or NaN: never selected
     if (v < best || (v == best && c < bi)) best = v, bi = c;
   }
   sv[tid] = best;
@@ -1463,7 +1454,7 @@ __global__ void k_argmin(const double* __restrict__ fom, int C, int* __restrict_
     }
     __syncthreads();
   }
-  if (tid == 0) *out = (si[0] == 0x7fffffff) ? 0 : si[0];
+  if (tid == 0) *out = (si[0] == 0x7fffffff) ? -1 : si[0];  // -1: no candidate has a finite FoM
 }
 
 // ------------------------------------------------------------------ launchers

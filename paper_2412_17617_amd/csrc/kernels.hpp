@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <cmath>
 #include <cstdint>
 
 #include "pxd.h"
@@ -111,6 +112,32 @@ __host__ __device__ inline SlotLayout slot_layout(int nmax, int P, bool mixed) {
     s.bytes = s.x_off + up((size_t)nmax * P * 16, 256);
   }
   return s;
+}
+
+// One step's verdict of the mixed-precision refinement (the stop and give-up
+// rule the kernels apply).  m: the largest change of any S entry the step
+// would make; m_prev: the same for the previous step (0 before the first);
+// target: the smallest ir_tol |S_ij| + floor over the entries.  The observed
+// contraction rho = m / m_prev (1 on the first step, so at least two steps are
+// taken) bounds the error left in every entry by m rho / (1 - rho).  Returns
+// 1 when that bound is below the target (and rho < 0.9), 2 when from the
+// third step on the contraction cannot bring it there within ir_max steps
+// (rho >= 1, a NaN, or more steps needed than remain: the FP64 path takes
+// the item), else 0 (take another step).
+__host__ __device__ inline int refine_verdict(int iters, int ir_max, double m, double m_prev, double target) {
+  const double rho = (iters == 1) ? 1.0 : (m_prev > 0.0 ? m / m_prev : 0.0);
+  const double left = m * rho / (1.0 - rho);
+  const bool ok = rho < 0.9 && left <= target;
+  if (ok) return 1;
+  if (iters >= 3) {
+    if (!(rho < 1.0) || !(left == left)) return 2;
+    if (rho > 0.0 && left > 0.0) {
+      // after k more steps the estimate is left rho^k
+      const double k_needed = log(target / left) / log(rho);
+      if (iters + k_needed > (double)ir_max) return 2;
+    }
+  }
+  return 0;
 }
 
 // Rows of the register-resident sub-panel per thread for a given active size.

@@ -88,6 +88,7 @@ _SIGS = {
     "pxd_expand": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "pxd_gather": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP]),
     "pxd_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
+    "pxd_refine_verdict": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double]),
     "pxd_evaluate_maps": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "pxd_evaluate_maps_device": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "pxd_autotune": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, C.c_int32, _VP]),
@@ -134,6 +135,15 @@ def _check(rc, ctx=None):
     if rc != OK:
         msg = lib().pxd_last_error(ctx)
         raise PxdError(rc, msg.decode() if msg else "")
+
+
+def refine_verdict(iters, ir_max, m, m_prev, target):
+    """The mixed-precision refinement's stop / give-up rule for one step
+    (pxd_refine_verdict): 1 converged, 2 hand to FP64, 0 continue."""
+    rc = lib().pxd_refine_verdict(iters, ir_max, m, m_prev, target)
+    if rc < 0:
+        _check(rc)
+    return rc
 
 
 class Problem:

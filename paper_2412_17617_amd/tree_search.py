@@ -15,7 +15,10 @@ Readings where the algorithm is silent: all nodes of one depth expand the same
 pixel; the restart happens when the count saturates at the deepest depth; the
 evaluation budget counts every candidate evaluated.  Optionally a surrogate
 (``Surrogate``) ranks the deepest level and only its best k leaves are solved;
-the exact evaluator still judges every accepted change.  Solving the trees
+the exact evaluator still judges every accepted change and, when none of
+those k leaves improves, solves the rest of the level before the iteration
+counts as a failure.  Candidates with a failed solve (negative status) are
+never selected.  Solving the trees
 by the low-rank flip evaluation from the current map's inverse (``lowrank``)
 is switched off: its one GPU run inside this driver made a memory fault
 whose cause has not been shown, so the option raises.
@@ -76,6 +79,26 @@ class TreeSearch:
         cells = np.concatenate(cells).astype(np.int32) if cells else np.zeros(0, np.int32)
         return np.asarray(offs, np.int32), cells, start, len(offs) - 1
 
+    @staticmethod
+    def _valid(Fc, st):
+        """FoM of the evaluated candidates with every failed one (negative
+        status: singular, non-finite, outside the size bound) at +inf, so
+        that it can neither be the arg min nor be accepted."""
+        Fc = np.array(Fc, np.float64)
+        Fc[np.asarray(st) < 0] = np.inf
+        return Fc
+
+    def _solve_leaves(self, P, offs, cells, idx, res):
+        """Exact FoM of the tree nodes idx (flip lists relative to P)."""
+        if len(idx) == 0:
+            return np.zeros(0)
+        sub = np.zeros(len(idx) + 1, np.int32)
+        sub[1:] = np.cumsum([offs[i + 1] - offs[i] for i in idx])
+        sc = np.concatenate([cells[offs[i]:offs[i + 1]] for i in idx]).astype(np.int32)
+        _, Fl, st, _ = self._eval(P, sub, sc, want_S=False)
+        res.evaluations += len(idx)
+        return self._valid(Fl, st)
+
     def _fom(self, m):
         _, F, _, _ = self._eval(m, np.array([0, 0], np.int32), np.zeros(0, np.int32), want_S=False)
         return float(F[0])
@@ -83,7 +106,8 @@ class TreeSearch:
     def run(self, start_map, pixel_order, restart_maps, max_evals: int, prefilter=None) -> SearchResult:
         """prefilter: None, or (surrogate, k, rank) where rank(surrogate, P,
         offsets, cells) returns the surrogate's predicted FoM of each
-        candidate; then only the best k of the deepest level are solved."""
+        candidate; then only the best k of the deepest level are solved, and
+        the rest of that level only when none of those k improves."""
         P = np.array(start_map, np.uint8)
         F = self._fom(P)
         res = SearchResult(F, P.copy(), 1)
@@ -101,23 +125,25 @@ class TreeSearch:
                 _, Fc, st, _ = self._eval(P, offs, cells, want_S=False)
                 res.evaluations += len(offs) - 1
                 leaves = np.arange(lo, hi)
-                Fl = Fc[lo:hi]
+                Fl = self._valid(Fc[lo:hi], st[lo:hi])
             else:
+                # the surrogate scores the whole tree; only the deepest level
+                # decides, so only its best k leaves are solved exactly
                 sur, k, rank = prefilter
-                upper = offs[:lo + 1]  # the levels above the leaves are solved exactly
-                if lo > 0:
-                    self._eval(P, upper, cells[:upper[-1]], want_S=False)
-                    res.evaluations += lo
                 pred = rank(sur, P, offs, cells)[lo:hi]
-                pick = np.argsort(pred, kind="stable")[:k] + lo
-                sub = np.zeros(len(pick) + 1, np.int32)
-                sub[1:] = np.cumsum([offs[i + 1] - offs[i] for i in pick])
-                sc = np.concatenate([cells[offs[i]:offs[i + 1]] for i in pick]).astype(np.int32)
-                _, Fl, st, _ = self._eval(P, sub, sc, want_S=False)
-                res.evaluations += len(pick)
+                order_l = np.argsort(pred, kind="stable") + lo
+                pick = order_l[:k]
+                Fl = self._solve_leaves(P, offs, cells, pick, res)
                 leaves = pick
+                if not (np.min(Fl) < F) and len(order_l) > len(pick):
+                    # no verified leaf improves: the exact solve stays the
+                    # fallback, so the rest of the level is solved before
+                    # this iteration counts as a failure
+                    rest = order_l[len(pick):]
+                    Fl = np.concatenate([Fl, self._solve_leaves(P, offs, cells, rest, res)])
+                    leaves = np.concatenate([pick, rest])
             k = int(np.argmin(Fl))  # lowest index among equal minima
-            if Fl[k] < F:
+            if np.isfinite(Fl[k]) and Fl[k] < F:
                 leaf = leaves[k]
                 P = P.copy()
                 P[cells[offs[leaf]:offs[leaf + 1]]] ^= 1

@@ -162,3 +162,32 @@ def test_full_batch_sampled():
     assert np.all(status == 0)
     assert dS <= S_TOL
     assert np.abs(S - S_d).max() <= S_TOL
+
+
+def test_cache_survives_a_refused_call():
+    """A low-rank call refused with ESHAPE (base map above the kernels' 2,048
+    limit) after a valid call overwrites the base active list; the next call
+    on the earlier base map must recompute its inverse, not pair the old
+    inverse with the new list.  20 x 20 x 2 parent (host fill) at two
+    frequencies; the all-on map has N = M = 2,371."""
+    spec = get_spec("batched20")
+    pb = pxd.Problem.from_spec(spec)
+    freqs = spec.freqs[[30, 60]]
+    Z = pb.fill(freqs, n_threads=8)
+    ev = pxd.Evaluator()
+    ev.load_parent(Z, freqs)
+    ev.load_problem(pb, spec.z0)
+    ev.set_fom_paper()
+    base = spec.base_map()
+    off, cells = flip_groups([[0], [17], [401], [799], [250, 251]])
+    S1, F1, _, _ = ev.evaluate_flips_lowrank(base, off, cells)
+    with pytest.raises(pxd.PxdError) as e:
+        ev.evaluate_flips_lowrank(np.ones(spec.n_cells, np.uint8), off, cells)
+    assert e.value.code == pxd.ESHAPE
+    S2, F2, st2, _ = ev.evaluate_flips_lowrank(base, off, cells)
+    assert ev.stats()["base_reused"] == 0
+    S_d, F_d, _, _ = ev.evaluate_flips(base, off, cells)
+    ev.close()
+    assert np.all(st2 == 0)
+    assert np.abs(S2 - S_d).max() <= S_TOL
+    assert np.abs(S2 - S1).max() <= S_TOL

@@ -161,6 +161,17 @@ def test_status_codes_are_reported():
     ev, _ = make_evaluator(spec, Zs, freqs)
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     assert status[0] == pxd.STATUS_OK and status[1] == pxd.STATUS_SINGULAR
+    # a failed candidate can never be selected (Algorithm 1 takes the arg min
+    # of valid FoM values): its FoM is +inf and the argmin is the valid one
+    assert np.isfinite(F[0]) and F[1] == np.inf and am == 0
+    # listed first, the singular candidate still loses to the regular one
+    off2, cells2 = single_flips([1, 0])
+    S, F, status, am = ev.evaluate_flips(base, off2, cells2)
+    assert status[0] == pxd.STATUS_SINGULAR and F[0] == np.inf and am == 1
+    # no valid candidate at all: argmin -1
+    off3, cells3 = single_flips([1, 2])
+    S, F, status, am = ev.evaluate_flips(base, off3, cells3)
+    assert np.all(status == pxd.STATUS_SINGULAR) and np.all(F == np.inf) and am == -1
     ev.close()
     Zn = Z.copy()
     Zn[2, 3, 4] = np.nan
@@ -168,6 +179,7 @@ def test_status_codes_are_reported():
     ev, _ = make_evaluator(spec, Zn, freqs)
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     assert np.all(status == pxd.STATUS_NONFINITE)
+    assert np.all(F == np.inf) and am == -1
     ev.close()
 
 
