@@ -140,7 +140,23 @@ typedef struct pxd_options {
   int32_t wg_per_cu;       /* persistent workgroups per compute unit: 1 or 2 (0 = tuned, else 2) */
   int32_t half_subpanel;   /* register sub-panel of the LU: 1 full width, 2 half width (0 = tuned, else full) */
   int32_t schedule;        /* PXD_SCHED_* */
+  int32_t lu_path;         /* PXD_PATH_*: which dense LU solves the items */
+  int32_t tile_kb;         /* tiled path: block-column width 64 or 128 (0 = tuned, else 64) */
+  double ws_gib;           /* tiled path: workspace cap in GiB (0 = 80 % of the free device memory,
+                              at most 64 GiB); fixes how many items are factored together */
 } pxd_options;
+
+/* Dense LU of the evaluation (Eq. 2).  Persistent: one workgroup per item,
+ * the whole factorisation and solve in one persistent launch over all items
+ * (active sizes up to 2,048).  Tiled: the items are factored in chunks, in
+ * lock step, one launch per step of each block column with many workgroups
+ * per item (a panel kernel per item, then the interchanges and U12 solve and
+ * the trailing-matrix update tiled over the item's columns / output tiles);
+ * active sizes up to 4,096; not available in graphs or the no-allocation
+ * entry point. */
+#define PXD_PATH_AUTO 0       /* tuned value for the size class, else persistent up to 2,048 and tiled above */
+#define PXD_PATH_PERSISTENT 1
+#define PXD_PATH_TILED 2
 
 typedef struct pxd_ctx pxd_ctx;
 

@@ -56,6 +56,8 @@ struct EvalBufs {
 // Launch configuration chosen per (precision, size class Q).
 struct Tuning {
   int wg_per_cu = 2, half_sb = 0, schedule = PXD_SCHED_FREQ_MAJOR;
+  bool tiled = false;  // dense LU path (PXD_PATH_TILED when true)
+  int tile_kb = 0;     // tiled path: block-column width (0 = default 64)
   bool valid = false;
   double ms = 0;
 };
@@ -90,6 +92,10 @@ struct pxd_ctx {
   pxd_stats stats{};
   bool stats_pending_counts = false;
   bool stats_lowrank = false;  // the last call was a low-rank one (stage events differ)
+  const int* stats_counts = nullptr;  // device counters of the last dense call ([1] fallbacks, [2] refinement steps)
+  // tiled path: item order of the call (host copy) and its device copy
+  std::vector<int> h_items, h_fb;
+  DevBuf tl_items;
   // autotuning: tuned[precision][size class]; `forced` overrides during a tuning sweep
   Tuning tuned[kPrecisions][kSizeClasses];
   const Tuning* forced = nullptr;
@@ -136,6 +142,151 @@ Tuning resolve(const pxd_ctx* ctx, int Q) {
   return r;
 }
 
+// Whether the batch's dense solves go to the tiled LU: the option, else the
+// tuned choice for the size class, else tiled only above the persistent
+// kernels' 2,048 limit.
+bool use_tiled(const pxd_ctx* ctx, int nmax) {
+  if (ctx->opt.lu_path == PXD_PATH_PERSISTENT) return false;
+  if (ctx->opt.lu_path == PXD_PATH_TILED || nmax > 2048) return true;
+  if (ctx->forced) return ctx->forced->tiled;
+  const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(pxd::rows_per_thread(nmax))];
+  return t.valid && t.tiled;
+}
+
+int tile_kb(const pxd_ctx* ctx, int nmax) {
+  if (ctx->opt.tile_kb == 64 || ctx->opt.tile_kb == 128) return ctx->opt.tile_kb;
+  if (ctx->forced && ctx->forced->tile_kb) return ctx->forced->tile_kb;
+  const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(pxd::rows_per_thread(nmax))];
+  return (t.valid && t.tile_kb) ? t.tile_kb : 64;
+}
+
+// Workspace cap of the tiled path in bytes: the option, else 80 % of the
+// device memory that is free or already held as workspace, at most 64 GiB.
+size_t tiled_ws_cap(const pxd_ctx* ctx, size_t held) {
+  if (ctx->opt.ws_gib > 0) return (size_t)(ctx->opt.ws_gib * (double)(1ull << 30));
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
+  return std::min<size_t>((size_t)(0.8 * (double)(fr + held)), size_t(64) << 30);
+}
+
+// Factor and solve the items `list[0 .. n)` (c * F + f) with the tiled LU in
+// chunks of at most `bmax` items whose slots fit the workspace.  mixed: the
+// complex64 factor and refinement (items that do not settle are appended to
+// fb_list); else the FP64 augmented system (fallback: report FALLBACK).
+int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const std::vector<int>& list,
+              const int* Nc, const int* Ilist, int* cnt, int* item_status, int* fb_list, double2* d_S, bool mixed,
+              bool fallback_mode) {
+  const int F = ctx->F, P = ctx->P;
+  const int n = (int)list.size();
+  if (n == 0) return PXD_OK;
+  int nmax_all = 0;
+  for (int it : list) nmax_all = std::max(nmax_all, ctx->hNc[it / F]);
+  const pxd::TlLayout lay_all = pxd::tl_layout(nmax_all, P, mixed);
+  const size_t cap = tiled_ws_cap(ctx, b.ws.bytes);
+  const int bmax = (int)std::min<size_t>({(size_t)n, (size_t)4 * ctx->n_cu, cap / lay_all.bytes});
+  if (bmax < 1)
+    return ctx->fail(PXD_ENOMEM, "tiled LU: one item's workspace (" + std::to_string(lay_all.bytes) +
+                                     " bytes) exceeds the workspace cap (" + std::to_string(cap) + " bytes)");
+  HIPCHK(ctx, b.ws.ensure(lay_all.bytes * (size_t)bmax));
+  const int kb = tile_kb(ctx, nmax_all);
+  pxd::TlParams tp{};
+  tp.Z128 = ctx->Z128.as<double2>();
+  tp.Z64 = ctx->Z64.as<float2>();
+  tp.M = ctx->M, tp.F = F, tp.P = P;
+  tp.Nc = Nc;
+  tp.Ilist = Ilist;
+  tp.port_len = ctx->plen.as<double>();
+  tp.z0 = ctx->z0;
+  tp.ws = b.ws.as<char>();
+  tp.mixed = mixed ? 1 : 0;
+  tp.kb = kb;
+  tp.half = ctx->opt.precision == PXD_PREC_MIXED_BF16 ? PXD_HALF_BF16
+            : ctx->opt.precision == PXD_PREC_MIXED_F16 ? PXD_HALF_F16 : PXD_HALF_NONE;
+  tp.S = d_S;
+  tp.status = item_status;
+  tp.fallback_mode = fallback_mode ? 1 : 0;
+  tp.ir_max = ctx->opt.ir_max_iter;
+  tp.ir_tol = ctx->opt.ir_tol;
+  tp.ir_iters = cnt + 2;
+  tp.fb_count = cnt + 1;
+  tp.fb_list = fb_list;
+  HIPCHK(ctx, pxd::tl_prepare(tp, nmax_all));
+  for (int i0 = 0; i0 < n; i0 += bmax) {
+    const int B = std::min(bmax, n - i0);
+    int nmax = 0;
+    for (int i = i0; i < i0 + B; ++i) nmax = std::max(nmax, ctx->hNc[list[i] / F]);
+    tp.items = d_list + i0;
+    tp.B = B;
+    tp.lay = pxd::tl_layout(nmax, P, mixed);
+    tp.slot_bytes = tp.lay.bytes;
+    const int ne_max = mixed ? nmax : nmax - P;
+    HIPCHK(ctx, pxd::tl_gather(s, tp, nmax));
+    for (int K = 0; K < ne_max; K += kb) {
+      HIPCHK(ctx, pxd::tl_panel(s, tp, K, nmax));
+      HIPCHK(ctx, pxd::tl_trsm(s, tp, K, nmax));
+      HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax));
+    }
+    HIPCHK(ctx, pxd::tl_finish(s, tp, nmax));
+  }
+  return PXD_OK;
+}
+
+// The rest of an evaluation whose dense solves go to the tiled LU (active
+// sizes known on the host): item order, chunks, FP64 re-solve of the items
+// the mixed path hands over, FoM and argmin.
+int evaluate_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, int C, const int* Nc, const int* Ilist, int* cnt,
+                   int* item_status, int* fb_list, double2* d_S, double* d_fom, int* d_cand_status, int* d_argmin,
+                   int nmin, int nmax) {
+  const bool mixed = ctx->opt.precision != PXD_PREC_FP64;
+  const int F = ctx->F, P = ctx->P;
+  const long long items = (long long)C * F;
+  // frequency-major (largest candidate first within a frequency) or size-major
+  // (largest first over all items): either way a chunk holds items of close sizes
+  std::vector<int>& order = ctx->h_items;
+  order.resize(items);
+  std::vector<int> cand(C);
+  for (int c = 0; c < C; ++c) cand[c] = c;
+  std::stable_sort(cand.begin(), cand.end(), [&](int a, int b2) { return ctx->hNc[a] > ctx->hNc[b2]; });
+  const Tuning tune = resolve(ctx, pxd::rows_per_thread(std::min(nmax, 2048)));
+  if (tune.schedule == PXD_SCHED_SIZE_MAJOR) {
+    for (int r = 0; r < C; ++r)
+      for (int f = 0; f < F; ++f) order[(size_t)r * F + f] = cand[r] * F + f;
+  } else {
+    for (int f = 0; f < F; ++f)
+      for (int r = 0; r < C; ++r) order[(size_t)f * C + r] = cand[r] * F + f;
+  }
+  HIPCHK(ctx, ctx->tl_items.ensure(sizeof(int) * (size_t)items));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->tl_items.p, order.data(), sizeof(int) * (size_t)items, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, pxd::launch_fill_int(s, cnt, 8, 0));
+  int rc = run_tiled(ctx, b, s, ctx->tl_items.as<int>(), order, Nc, Ilist, cnt, item_status, fb_list, d_S, mixed,
+                     false);
+  if (rc) return rc;
+  HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+  if (mixed) {  // FP64 re-solve of the items refinement could not settle
+    int nfb = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&nfb, cnt + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (nfb > 0) {
+      ctx->h_fb.resize(nfb);
+      HIPCHK(ctx, hipMemcpyAsync(ctx->h_fb.data(), fb_list, sizeof(int) * nfb, hipMemcpyDeviceToHost, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      rc = run_tiled(ctx, b, s, fb_list, ctx->h_fb, Nc, Ilist, cnt, item_status, fb_list, d_S, false, true);
+      if (rc) return rc;
+    }
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+  HIPCHK(ctx, pxd::launch_fom(s, d_S, C, F, P, ctx->terms.as<pxd_fom_term>(), ctx->term_fac.as<double>(),
+                              ctx->n_terms, ctx->band.as<int8_t>(), item_status, d_fom, d_cand_status));
+  if (d_argmin) HIPCHK(ctx, pxd::launch_argmin(s, d_fom, C, d_argmin));
+  HIPCHK(ctx, hipEventRecord(ctx->ev[4], s));
+  ctx->stats.items = items;
+  ctx->stats.max_active = nmax;
+  ctx->stats.min_active = nmin;
+  ctx->stats_pending_counts = mixed;
+  ctx->stats_counts = cnt;
+  return PXD_OK;
+}
+
 // Enqueue one evaluation of C candidates on stream s.  nmax_bound > 0: the
 // launch is sized for that bound without reading the active sizes back (as a
 // graph needs); otherwise they are read back to size it exactly.  Events and
@@ -151,63 +302,77 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   const int M = ctx->M, F = ctx->F, P = ctx->P;
   if (events) ctx->stats = pxd_stats{}, ctx->stats_lowrank = false;
   if (C == 0) return PXD_OK;
+  const long long items = (long long)C * F;
+  int *Nc, *Ilist, *order, *cnt, *item_status, *fb_list = nullptr;
   HIPCHK(ctx, b.Nc.ensure(sizeof(int) * C));
   HIPCHK(ctx, b.Ilist.ensure(sizeof(int) * (size_t)C * M));
   HIPCHK(ctx, b.order.ensure(sizeof(int) * C));
   HIPCHK(ctx, b.counter.ensure(sizeof(int) * 8));
-  HIPCHK(ctx, b.item_status.ensure(sizeof(int) * (size_t)C * F));
+  HIPCHK(ctx, b.item_status.ensure(sizeof(int) * (size_t)items));
+  if (mixed) HIPCHK(ctx, b.fb_list.ensure(sizeof(int) * (size_t)items));
+  Nc = b.Nc.as<int>(), Ilist = b.Ilist.as<int>(), order = b.order.as<int>(), cnt = b.counter.as<int>();
+  item_status = b.item_status.as<int>(), fb_list = b.fb_list.as<int>();
   if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
   HIPCHK(ctx, pxd::launch_expand(s, d_base, ctx->n_cells, base_stride, d_off, d_cells, C, ctx->cell_a.as<int>(),
-                                 ctx->cell_b.as<int>(), M, b.Nc.as<int>(), b.Ilist.as<int>()));
-  HIPCHK(ctx, pxd::launch_order(s, b.Nc.as<int>(), C, b.order.as<int>()));
+                                 ctx->cell_b.as<int>(), M, Nc, Ilist));
+  HIPCHK(ctx, pxd::launch_order(s, Nc, C, order));
   int nmax = nmax_bound, nmin = P;
   if (nmax_bound <= 0) {
     // the largest active size picks the kernel variant and the slot size
     ctx->hNc.resize(C);
-    HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data(), b.Nc.p, sizeof(int) * C, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data(), Nc, sizeof(int) * C, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     nmax = *std::max_element(ctx->hNc.begin(), ctx->hNc.end());
     nmin = *std::min_element(ctx->hNc.begin(), ctx->hNc.end());
     if (nmin < P) return ctx->fail(PXD_ESHAPE, "candidate with fewer active functions than ports");
   }
-  if (nmax > 2048) return ctx->fail(PXD_ESHAPE, "active size above 2048 is not supported");
+  const bool tiled = use_tiled(ctx, nmax);
+  if (tiled) {
+    if (nmax_bound > 0)
+      return ctx->fail(PXD_ESHAPE, "the tiled LU (active sizes above 2,048) is not available in graphs");
+    if (nmax > pxd::tl_max_active())
+      return ctx->fail(PXD_ESHAPE, "active size above " + std::to_string(pxd::tl_max_active()) + " is not supported");
+    if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+    return evaluate_tiled(ctx, b, s, C, Nc, Ilist, cnt, item_status, fb_list, d_S, d_fom, d_cand_status, d_argmin,
+                          nmin, nmax);
+  }
+  if (nmax > 2048) return ctx->fail(PXD_ESHAPE, "active size above 2048 needs the tiled LU (lu_path)");
   if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
 
   const Tuning tune = resolve(ctx, pxd::rows_per_thread(nmax));
-  const long long items = (long long)C * F;
   int grid = (int)std::min<long long>(items, (long long)ctx->n_cu * tune.wg_per_cu);
   const pxd::SlotLayout lay_p = pxd::slot_layout(nmax, P, false);
   const pxd::SlotLayout lay_m = pxd::slot_layout(nmax, P, true);
   // the mixed path re-solves unrefined items with the FP64 kernel in the same slots
   const size_t slot = mixed ? std::max(lay_p.bytes, lay_m.bytes) : lay_p.bytes;
   HIPCHK(ctx, b.ws.ensure(slot * (size_t)grid));
-  if (mixed) HIPCHK(ctx, b.fb_list.ensure(sizeof(int) * (size_t)items));
+  char* ws = b.ws.as<char>();
 
   pxd::EvalParams ep{};
   ep.Z128 = ctx->Z128.as<double2>();
   ep.Z64 = ctx->Z64.as<float2>();
   ep.M = M, ep.F = F, ep.P = P, ep.C = C;
-  ep.Nc = b.Nc.as<int>();
-  ep.Ilist = b.Ilist.as<int>();
-  ep.order = b.order.as<int>();
+  ep.Nc = Nc;
+  ep.Ilist = Ilist;
+  ep.order = order;
   ep.port_len = ctx->plen.as<double>();
   ep.z0 = ctx->z0;
   ep.n_items = (int)items;
   ep.item_list = nullptr;
-  ep.counter = b.counter.as<int>();
-  ep.ws = b.ws.as<char>();
+  ep.counter = cnt;
+  ep.ws = ws;
   ep.slot_bytes = slot;
   ep.ld = mixed ? lay_m.ld : lay_p.ld;
   ep.nmax = nmax;
   ep.S = d_S;
-  ep.status = b.item_status.as<int>();
+  ep.status = item_status;
   ep.ir_max = ctx->opt.ir_max_iter;
   ep.ir_tol = ctx->opt.ir_tol;
   ep.schedule = tune.schedule;
   ep.half = ctx->opt.precision == PXD_PREC_MIXED_BF16 ? PXD_HALF_BF16
             : ctx->opt.precision == PXD_PREC_MIXED_F16 ? PXD_HALF_F16 : PXD_HALF_NONE;
-  int* cnt = b.counter.as<int>();  // [0] work, [1] fallback count, [2] refinement steps, [3] fallback work
-  ep.fb_list = b.fb_list.as<int>();
+  // cnt: [0] work, [1] fallback count, [2] refinement steps, [3] fallback work
+  ep.fb_list = fb_list;
   ep.fb_count = cnt + 1;
   ep.ir_iters = cnt + 2;
   HIPCHK(ctx, pxd::launch_fill_int(s, cnt, 8, 0));
@@ -229,8 +394,7 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
     if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
   }
   HIPCHK(ctx, pxd::launch_fom(s, d_S, C, F, P, ctx->terms.as<pxd_fom_term>(), ctx->term_fac.as<double>(),
-                              ctx->n_terms, ctx->band.as<int8_t>(), b.item_status.as<int>(), d_fom,
-                              d_cand_status));
+                              ctx->n_terms, ctx->band.as<int8_t>(), item_status, d_fom, d_cand_status));
   if (d_argmin) HIPCHK(ctx, pxd::launch_argmin(s, d_fom, C, d_argmin));
   if (events) {
     HIPCHK(ctx, hipEventRecord(ctx->ev[4], s));
@@ -238,6 +402,7 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
     ctx->stats.max_active = nmax;
     ctx->stats.min_active = nmin;
     ctx->stats_pending_counts = mixed;
+    ctx->stats_counts = cnt;
   }
   return PXD_OK;
 }
@@ -502,7 +667,8 @@ void pxd_destroy(pxd_ctx* ctx) {
                     &ctx->band, &ctx->base, &ctx->off, &ctx->cells, &ctx->S, &ctx->cand_status, &ctx->fom,
                     &ctx->argmin})
     b->release();
-  for (DevBuf* b : {&ctx->lr_G, &ctx->lr_IB, &ctx->lr_NB, &ctx->lr_pos, &ctx->lr_bstat, &ctx->lr_ws, &ctx->lr_cnt})
+  for (DevBuf* b : {&ctx->lr_G, &ctx->lr_IB, &ctx->lr_NB, &ctx->lr_pos, &ctx->lr_bstat, &ctx->lr_ws, &ctx->lr_cnt,
+                    &ctx->tl_items})
     b->release();
   ctx->eb.release();
   for (auto& ev : ctx->ev)
@@ -884,6 +1050,10 @@ void pxd_graph_destroy(pxd_graph* g) {
     (void)hipStreamSynchronize(g->ctx->stream);
     (void)hipDeviceSynchronize();
   }
+  if (g->ctx && g->ctx->stats_counts == g->eb.counter.as<int>()) {  // the counters go with the graph
+    g->ctx->stats_counts = nullptr;
+    g->ctx->stats_pending_counts = false;
+  }
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   g->eb.release();
@@ -971,7 +1141,7 @@ int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out) {
     if (ctx->stats_pending_counts && hipEventElapsedTime(&d, ctx->ev[2], ctx->ev[3]) == hipSuccess) {
       out->ms_fallback = d;
       int h[4] = {0, 0, 0, 0};
-      if (hipMemcpy(h, ctx->eb.counter.p, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
+      if (ctx->stats_counts && hipMemcpy(h, ctx->stats_counts, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
         out->fallbacks = h[1];
         out->ir_iterations = h[2];
       }

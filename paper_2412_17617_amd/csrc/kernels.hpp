@@ -140,6 +140,76 @@ __host__ __device__ inline int refine_verdict(int iters, int ir_max, double m, d
   return 0;
 }
 
+// ------------------------------------------------------------------ tiled LU
+//
+// Large active sizes: the items of a chunk are factored in lock step, one
+// kernel launch per step of each block column, many workgroups per item.
+
+constexpr int kTlKbMax = 128;  // widest block column of the tiled LU
+
+// Per-item slot of the tiled path: the item's matrix (row-major, ld), its
+// pivots, an auxiliary block (flags, the current block column's touched rows
+// and their sources), the inverse of the block column's unit-lower diagonal
+// block (kTlKbMax x kTlKbMax) and, in the mixed modes, the FP64 solution.
+struct TlLayout {
+  int ld;
+  size_t piv_off, aux_off, li_off, x_off, bytes;
+};
+__host__ __device__ inline TlLayout tl_layout(int nmax, int P, bool mixed) {
+  auto up = [](size_t v, size_t a) -> size_t { return (v + a - 1) / a * a; };
+  TlLayout s{};
+  const size_t es = mixed ? 8 : 16;
+  s.ld = (int)up(mixed ? nmax : nmax + P, 4);
+  size_t o = up((size_t)nmax * s.ld * es, 256);
+  s.piv_off = o;
+  o += up((size_t)nmax * 4, 256);
+  s.aux_off = o;
+  o += up((size_t)(4 + 4 * kTlKbMax) * 4, 256);
+  s.li_off = o;
+  o += up((size_t)kTlKbMax * kTlKbMax * es, 256);
+  s.x_off = o;
+  if (mixed) o += up((size_t)nmax * P * 16, 256);
+  s.bytes = o;
+  return s;
+}
+
+struct TlParams {
+  const double2* Z128;  // F x M x M parent (complex128)
+  const float2* Z64;    // its complex64 copy, or null (the gather then rounds Z128)
+  int M, F, P;
+  const int* Nc;        // active size per candidate
+  const int* Ilist;     // C x M active lists
+  const int* items;     // this chunk's items (c * F + f)
+  int B;                // items in the chunk
+  const double* port_len;
+  double z0;
+  char* ws;             // B slots of slot_bytes
+  size_t slot_bytes;
+  TlLayout lay;
+  int mixed;            // 0: FP64 augmented [Z_A | V] (eliminate N - P columns), 1: complex64 N x N
+  int kb;               // block-column width (64 or 128)
+  int half;             // mixed: operands of the trailing updates (PXD_HALF_*)
+  double2* S;           // C x F x P x P
+  int* status;          // C x F
+  int fallback_mode;    // FP64 re-solve of items the mixed path handed over: report FALLBACK
+  int ir_max;
+  double ir_tol;
+  int* ir_iters;
+  int* fb_count;
+  int* fb_list;
+};
+
+// Launches of one chunk.  K: first column of the block column; nmax: the
+// chunk's largest active size (sizes the grids); q: register rows per
+// thread of the panel (>= (nmax - K) / 256).
+hipError_t tl_gather(hipStream_t s, const TlParams& p, int nmax);
+hipError_t tl_panel(hipStream_t s, const TlParams& p, int K, int nmax);
+hipError_t tl_trsm(hipStream_t s, const TlParams& p, int K, int nmax);
+hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax);
+hipError_t tl_finish(hipStream_t s, const TlParams& p, int nmax);
+hipError_t tl_prepare(const TlParams& p, int nmax);  // kernel attributes (outside capture)
+int tl_max_active();                                 // largest active size the tiled path takes
+
 // Rows of the register-resident sub-panel per thread for a given active size.
 __host__ __device__ inline int rows_per_thread(int nmax) { return (nmax + 255) / 256; }
 

@@ -1,0 +1,510 @@
+// Tiled LU for large active sizes: the items of a chunk are factored in lock
+// step, one launch per step of each block column, with many workgroups per
+// item (Eq. 2's dense solve when one item's matrix is far larger than what
+// one compute unit can hold or stream efficiently).
+//
+// Per item the layout is that of the persistent evaluator: the matrix
+// row-major in its slot, ports ordered last, right-looking LU with partial
+// pivoting in block columns of kb (64 or 128), factored in 32-wide panels.
+// Per block column [K, K + kb):
+//   k_tl_panel   one workgroup per item: factor the block column over rows
+//                [K, N) (register sub-panels, interchanges applied across the
+//                block column), store the pivots, the inverse of its
+//                unit-lower diagonal block L11 and, for the columns to its
+//                right, which rows the block's interchanges touch and where
+//                each one's new content comes from;
+//   k_tl_trsm    per (item, 64- or 32-column tile): apply those interchanges
+//                to the tile and form U12 = L11^-1 A12 on MFMA;
+//   k_tl_update  per (item, output tile): A22 -= L21 U12, a complex GEMM of
+//                four real MFMA products on LDS-staged planar tiles.
+// Columns left of a block column are not permuted by later blocks (solves
+// replay the interchanges block by block), as in the persistent kernels.
+// Then per item: the port block and S (FP64 augmented system) or the
+// complex64 solve with FP64 refinement (mixed modes).
+#include "device.hpp"
+#include "kernels.hpp"
+#include "lu_device.hpp"
+
+namespace pxd {
+
+namespace {
+
+struct TlItem {
+  int c, f, N, Ne, ncols;
+};
+
+__device__ __forceinline__ TlItem tl_item(const TlParams& p, int b) {
+  const int it = p.items[b];
+  TlItem r;
+  r.c = it / p.F;
+  r.f = it - r.c * p.F;
+  r.N = p.Nc[r.c];
+  r.Ne = p.mixed ? r.N : r.N - p.P;
+  r.ncols = p.mixed ? r.N : r.N + p.P;
+  return r;
+}
+
+__device__ __forceinline__ int* tl_aux(const TlParams& p, int b) {
+  return reinterpret_cast<int*>(p.ws + (size_t)b * p.slot_bytes + p.lay.aux_off);
+}
+// aux: [0] zero-pivot flag, [1] touched-row count, tr[2 kTlKbMax], src[2 kTlKbMax]
+constexpr int kAuxTr = 4;
+constexpr int kAuxSrc = 4 + 2 * kTlKbMax;
+
+// ------------------------------------------------------------------ gather
+
+// Z_A = Z_f[I, I] (Eq. 5) with the Z0 loads of the port functions added on
+// the diagonal; FP64 path: the excitation columns V (1 V in each port gap)
+// appended.  16 rows per workgroup, 4 per wave.
+template <typename T, typename TP>
+__global__ __launch_bounds__(256) void k_tl_gather(TlParams p, const TP* __restrict__ Zpar) {
+  using R = decltype(T::x);
+  const int b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const TlItem t = tl_item(p, b);
+  const int r0 = blockIdx.x * 16;
+  if (blockIdx.x == 0 && tid == 0) {
+    int* aux = tl_aux(p, b);
+    aux[0] = 0;
+    aux[1] = 0;
+  }
+  if (r0 >= t.N) return;
+  T* W = reinterpret_cast<T*>(p.ws + (size_t)b * p.slot_bytes);
+  const int* I = p.Ilist + (size_t)t.c * p.M;
+  const TP* Zf = Zpar + (size_t)t.f * p.M * p.M;
+  const int P = p.P;
+  for (int rr = wid; rr < 16; rr += kWaves) {
+    const int r = r0 + rr;
+    if (r >= t.N) break;
+    const TP* zrow = Zf + (size_t)I[r] * p.M;
+    T* wrow = W + (size_t)r * p.lay.ld;
+    const int pi = r - (t.N - P);  // port index of this row, if it is a port row
+    const double load = (pi >= 0) ? p.z0 * p.port_len[pi] * p.port_len[pi] : 0.0;
+    for (int s = lane; s < t.N; s += 64) {
+      const TP v = zrow[I[s]];
+      const double re = (double)v.x + ((s == r) ? load : 0.0);
+      wrow[s] = T{(R)re, (R)v.y};
+    }
+    if (!p.mixed && lane < P) wrow[t.N + lane] = T{(pi == lane) ? (R)p.port_len[lane] : (R)0, (R)0};
+  }
+}
+
+// ------------------------------------------------------------------ panel
+
+template <typename R, int Q, int SB>
+__global__ __launch_bounds__(256) void k_tl_panel(TlParams p, int K) {
+  using T = typename Cx<R>::T;
+  __shared__ LuShared<R> sm;
+  __shared__ T sY[NB * NB];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const TlItem t = tl_item(p, b);
+  if (K >= t.Ne) return;
+  const int kbb = min(p.kb, t.Ne - K), Kend = K + kbb;
+  const int ld = p.lay.ld;
+  char* slot = p.ws + (size_t)b * p.slot_bytes;
+  T* W = reinterpret_cast<T*>(slot);
+  int* piv = reinterpret_cast<int*>(slot + p.lay.piv_off);
+  int* aux = reinterpret_cast<int*>(slot + p.lay.aux_off);
+  T* Li = reinterpret_cast<T*>(slot + p.lay.li_off);
+  if (tid == 0) sm.bad = aux[0];
+  __syncthreads();
+  for (int k = K; k < Kend; k += NB) {
+    const int kb = min(NB, Kend - k);
+    factor_panel<R, Q, SB>(W, ld, t.N, k, kb, sm);
+    for (int i = tid; i < kb; i += kThreads) {
+      sm.bpiv[k - K + i] = sm.piv[i];
+      piv[k + i] = sm.piv[i];
+    }
+    apply_swaps<T>(W, ld, k, kb, sm.piv, K, k);          // block columns left of the panel
+    swap_trsm<R>(W, ld, k, kb, k + kb, Kend, sm, sm.piv);  // and right of it, inside the block
+    trailing_update<R>(W, ld, k, kb, t.N, k + kb, Kend);
+    __syncthreads();
+  }
+  // rows the block's interchanges touch and the source of each one's final
+  // content: the interchanges applied in order to an identity map
+  if (tid == 0) {
+    aux[0] = sm.bad;
+    int* tr = aux + kAuxTr;
+    int* src = aux + kAuxSrc;
+    int n = kbb;
+    for (int i = 0; i < kbb; ++i) tr[i] = src[i] = K + i;
+    for (int i = 0; i < kbb; ++i) {
+      const int q = sm.bpiv[i];
+      if (q == K + i) continue;
+      int jq = q - K;
+      if (q >= Kend) {
+        jq = -1;
+        for (int j = kbb; j < n; ++j)
+          if (tr[j] == q) {
+            jq = j;
+            break;
+          }
+        if (jq < 0) {
+          tr[n] = src[n] = q;
+          jq = n++;
+        }
+      }
+      const int s0 = src[i];
+      src[i] = src[jq];
+      src[jq] = s0;
+    }
+    aux[1] = n;
+  }
+  // Li = L11^-1 (unit lower, kbb x kbb) by 32 x 32 blocks: the diagonal
+  // blocks' inverses by substitution, then block row bi, column bj < bi:
+  //   Li[bi][bj] = -Li[bi][bi] sum_{bj <= tb < bi} L[bi][tb] Li[tb][bj]
+  const int nbk = (kbb + NB - 1) / NB;
+  T* Lb = sm.buf;            // diagonal block of L (strictly lower part)
+  T* Db = sm.buf + NB * NB;  // its inverse
+  for (int bi = 0; bi < nbk; ++bi) {
+    const int r0 = K + bi * NB, kbi = min(NB, kbb - bi * NB);
+    for (int e = tid; e < NB * NB; e += kThreads) {
+      const int i = e / NB, j = e - i * NB;
+      Lb[e] = (i < kbi && j < i) ? W[(size_t)(r0 + i) * ld + r0 + j] : T{0, 0};
+      Db[e] = (i == j && i < kbi) ? T{1, 0} : T{0, 0};
+    }
+    __syncthreads();
+    for (int i = 1; i < kbi; ++i) {  // Db[i][j] = -sum_{j <= u < i} Lb[i][u] Db[u][j]
+      if (tid < i) {
+        const int j = tid;
+        T acc{0, 0};
+        for (int u = j; u < i; ++u) acc = cfms(acc, Lb[i * NB + u], Db[u * NB + j]);
+        Db[i * NB + j] = acc;
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < NB * NB; e += kThreads) {
+      const int i = e / NB, j = e - i * NB;
+      Li[(size_t)(bi * NB + i) * kTlKbMax + bi * NB + j] = Db[e];
+      for (int bj = bi + 1; bj < nbk; ++bj) Li[(size_t)(bi * NB + i) * kTlKbMax + bj * NB + j] = T{0, 0};
+    }
+    __syncthreads();
+    for (int bj = 0; bj < bi; ++bj) {
+      // Y = sum over the block columns tb in [bj, bi) of L[bi][tb] Li[tb][bj]
+      for (int e = tid; e < NB * NB; e += kThreads) {
+        const int i = e / NB, j = e - i * NB;
+        T acc{0, 0};
+        if (i < kbi)
+          for (int u = bj * NB; u < bi * NB; ++u)
+            acc = cfms(acc, W[(size_t)(r0 + i) * ld + K + u], Li[(size_t)u * kTlKbMax + bj * NB + j]);
+        sY[e] = acc;  // holds -Y
+      }
+      __syncthreads();
+      for (int e = tid; e < NB * NB; e += kThreads) {
+        const int i = e / NB, j = e - i * NB;
+        T acc{0, 0};
+        for (int u = 0; u <= i; ++u) acc = cfms(acc, Db[i * NB + u], sY[u * NB + j]);
+        Li[(size_t)(bi * NB + i) * kTlKbMax + bj * NB + j] = T{-acc.x, -acc.y};  // = Db (-Y)
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ interchanges + U12
+
+// One workgroup per (item, CT-column tile of [Kend, ncols)).  The block's
+// interchanges reach the tile as a gather from the source rows (all old
+// values are read before any is written), then U12 = L11^-1 (P A12) on MFMA:
+// the right-hand block in LDS, L11^-1 fragments from the slot (cache).
+template <typename R, int CT>
+__global__ __launch_bounds__(256) void k_tl_trsm(TlParams p, int K) {
+  using T = typename Cx<R>::T;
+  using MF = Mfma<R>;
+  using acc_t = typename MF::acc_t;
+  constexpr int SBS = CT + 16;  // LDS row stride (conflict-free B fragments)
+  constexpr int NSUB = CT / 16;
+  constexpr int MAXD = kTlKbMax * CT / kThreads;  // displaced (row, column) pairs per thread
+  __shared__ R Br[kTlKbMax * SBS], Bi[kTlKbMax * SBS];
+  const int b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const TlItem t = tl_item(p, b);
+  if (K >= t.Ne) return;
+  const int kbb = min(p.kb, t.Ne - K), Kend = K + kbb;
+  const int c0 = Kend + blockIdx.x * CT;
+  if (c0 >= t.ncols) return;
+  const int c1 = min(c0 + CT, t.ncols);
+  const int ld = p.lay.ld;
+  char* slot = p.ws + (size_t)b * p.slot_bytes;
+  T* W = reinterpret_cast<T*>(slot);
+  const int* aux = reinterpret_cast<const int*>(slot + p.lay.aux_off);
+  const int* tr = aux + kAuxTr;
+  const int* src = aux + kAuxSrc;
+  const T* Li = reinterpret_cast<const T*>(slot + p.lay.li_off);
+  const int ntouch = aux[1];
+  const int kpad = (kbb + 3) & ~3;
+  for (int e = tid; e < kpad * CT; e += kThreads) {
+    const int kr = e / CT, cc = e - kr * CT;
+    const T v = (kr < kbb && c0 + cc < c1) ? W[(size_t)src[kr] * ld + c0 + cc] : T{0, 0};
+    Br[kr * SBS + cc] = v.x;
+    Bi[kr * SBS + cc] = v.y;
+  }
+  T dv[MAXD];
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) {
+    const int e = tid + kThreads * i;
+    const int j = kbb + e / CT, cc = e % CT;
+    dv[i] = (j < ntouch && c0 + cc < c1) ? W[(size_t)src[j] * ld + c0 + cc] : T{0, 0};
+  }
+  __syncthreads();  // every old value has been read
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) {
+    const int e = tid + kThreads * i;
+    const int j = kbb + e / CT, cc = e % CT;
+    if (j < ntouch && c0 + cc < c1) W[(size_t)tr[j] * ld + c0 + cc] = dv[i];
+  }
+  const int nrs = (kbb + 15) >> 4;
+  for (int rs = wid; rs < nrs; rs += kWaves) {
+    acc_t cr[NSUB], ci[NSUB];
+#pragma unroll
+    for (int sn = 0; sn < NSUB; ++sn) {
+      cr[sn] = acc_t{0, 0, 0, 0};
+      ci[sn] = acc_t{0, 0, 0, 0};
+    }
+    const int row = 16 * rs + l16;
+    for (int kq = 0; kq < kpad / 4; ++kq) {
+      const int kk = 4 * kq + lk;
+      const T a = (row < kbb && kk < kbb) ? Li[(size_t)row * kTlKbMax + kk] : T{0, 0};
+#pragma unroll
+      for (int sn = 0; sn < NSUB; ++sn) {
+        const R br = Br[kk * SBS + 16 * sn + l16], bi = Bi[kk * SBS + 16 * sn + l16];
+        cr[sn] = MF::run(a.x, br, cr[sn]);
+        cr[sn] = MF::run(-a.y, bi, cr[sn]);
+        ci[sn] = MF::run(a.x, bi, ci[sn]);
+        ci[sn] = MF::run(a.y, br, ci[sn]);
+      }
+    }
+#pragma unroll
+    for (int sn = 0; sn < NSUB; ++sn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * rs + MF::row(lane, i), col = c0 + 16 * sn + l16;
+        if (r < kbb && col < c1) W[(size_t)(K + r) * ld + col] = T{cr[sn][i], ci[sn][i]};
+      }
+  }
+}
+
+// ------------------------------------------------------------------ trailing update
+
+// A22 -= L21 U12 for one TM x TN output tile of one item, rows [Kend, N),
+// columns [Kend, ncols).  Four waves in a 2 x 2 grid, each owning a
+// (TM/2) x (TN/2) block of 16 x 16 MFMA tiles (real and imaginary
+// accumulators).  L21 and U12 are staged in LDS as planar real/imaginary
+// tiles, KC columns of L21 (rows as stored, row stride KC + pad) and KC rows
+// of U12 (row stride TN + 16) at a time; the strides make the fragment reads
+// of a wave hit distinct banks.  The block id is remapped so that the tiles
+// of one item run on one XCD (workgroups are dealt to the XCDs in turn).
+template <typename R, int TM, int TN, int KC>
+__global__ __launch_bounds__(256, 2) void k_tl_update(TlParams p, int K, int tiles_m, int tiles_n) {
+  using T = typename Cx<R>::T;
+  using MF = Mfma<R>;
+  using acc_t = typename MF::acc_t;
+  constexpr int WM = TM / 2, WN = TN / 2, SM = WM / 16, SN = WN / 16;
+  constexpr int SA = (sizeof(R) == 4) ? KC + 4 : KC + 2;  // A row stride: 4 x odd (f32), 2 x odd (f64)
+  constexpr int SBS = TN + 16;
+  __shared__ R Ar[TM * SA], Ai[TM * SA], Br[KC * SBS], Bi[KC * SBS];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  // XCD-grouped block order
+  const int total = gridDim.x * gridDim.y;
+  const int lid = blockIdx.x + blockIdx.y * gridDim.x;
+  const int gid = (lid & 7) * (total >> 3) + (lid >> 3);
+  const int b = gid / gridDim.x, tile = gid - b * gridDim.x;
+  if (b >= p.B || tile >= tiles_m * tiles_n) return;
+  const TlItem t = tl_item(p, b);
+  if (K >= t.Ne) return;
+  const int kbb = min(p.kb, t.Ne - K), Kend = K + kbb;
+  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  const int r0 = Kend + tm * TM, c0 = Kend + tn * TN;
+  if (r0 >= t.N || c0 >= t.ncols) return;
+  const int ld = p.lay.ld;
+  T* W = reinterpret_cast<T*>(p.ws + (size_t)b * p.slot_bytes);
+  const int wm = wid & 1, wn = wid >> 1;
+  const int rw = r0 + wm * WM, cw = c0 + wn * WN;
+  acc_t cr[SM][SN], ci[SM][SN];
+#pragma unroll
+  for (int a = 0; a < SM; ++a)
+#pragma unroll
+    for (int s = 0; s < SN; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
+        const T v = (r < t.N && col < t.ncols) ? W[(size_t)r * ld + col] : T{0, 0};
+        cr[a][s][i] = v.x;
+        ci[a][s][i] = v.y;
+      }
+  for (int k0 = K; k0 < Kend; k0 += KC) {
+    __syncthreads();  // the previous stage is consumed
+#pragma unroll 2
+    for (int e = tid; e < TM * KC; e += kThreads) {
+      const int row = e / KC, kk = e - row * KC;
+      const int r = r0 + row, k = k0 + kk;
+      const T v = (r < t.N && k < Kend) ? W[(size_t)r * ld + k] : T{0, 0};
+      Ar[row * SA + kk] = v.x;
+      Ai[row * SA + kk] = v.y;
+    }
+#pragma unroll 2
+    for (int e = tid; e < KC * TN; e += kThreads) {
+      const int kr = e / TN, col = e - kr * TN;
+      const int k = k0 + kr, cc = c0 + col;
+      const T v = (k < Kend && cc < t.ncols) ? W[(size_t)k * ld + cc] : T{0, 0};
+      Br[kr * SBS + col] = v.x;
+      Bi[kr * SBS + col] = v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < KC / 4; ++kq) {
+      R ar[SM], ai[SM], br[SN], bi[SN];
+#pragma unroll
+      for (int a = 0; a < SM; ++a) {
+        const int row = wm * WM + 16 * a + l16;
+        ar[a] = Ar[row * SA + 4 * kq + lk];
+        ai[a] = Ai[row * SA + 4 * kq + lk];
+      }
+#pragma unroll
+      for (int s = 0; s < SN; ++s) {
+        const int col = wn * WN + 16 * s + l16;
+        br[s] = Br[(4 * kq + lk) * SBS + col];
+        bi[s] = Bi[(4 * kq + lk) * SBS + col];
+      }
+      // C -= A B:  Cr += (-Ar) Br + Ai Bi,  Ci += (-Ar) Bi + (-Ai) Br
+#pragma unroll
+      for (int a = 0; a < SM; ++a)
+#pragma unroll
+        for (int s = 0; s < SN; ++s) {
+          cr[a][s] = MF::run(-ar[a], br[s], cr[a][s]);
+          cr[a][s] = MF::run(ai[a], bi[s], cr[a][s]);
+          ci[a][s] = MF::run(-ar[a], bi[s], ci[a][s]);
+          ci[a][s] = MF::run(-ai[a], br[s], ci[a][s]);
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < SM; ++a)
+#pragma unroll
+    for (int s = 0; s < SN; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
+        if (r < t.N && col < t.ncols) W[(size_t)r * ld + col] = T{cr[a][s][i], ci[a][s][i]};
+      }
+}
+
+// ------------------------------------------------------------------ per-item finish
+
+// FP64 augmented system: the P x P port block left after eliminating the
+// first N - P columns, then S (Eqs. 6-7).
+__global__ __launch_bounds__(256) void k_tl_finish_plain(TlParams p) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const TlItem t = tl_item(p, b);
+  const double2* W = reinterpret_cast<const double2*>(p.ws + (size_t)b * p.slot_bytes);
+  const int* aux = tl_aux(p, b);
+  double2* Sout = p.S + ((size_t)t.c * p.F + t.f) * p.P * p.P;
+  int st = port_solve_and_s(W, p.lay.ld, t.N, p.P, p.port_len, p.z0, Sout);
+  if (tid == 0) {
+    if (aux[0] && st == PXD_STATUS_OK) st = PXD_STATUS_SINGULAR;
+    if (p.fallback_mode && st == PXD_STATUS_OK) st = PXD_STATUS_FALLBACK;
+    p.status[(size_t)t.c * p.F + t.f] = st;
+  }
+}
+
+// Mixed modes: complex64 solve and FP64 refinement of the factored item.
+__global__ __launch_bounds__(256) void k_tl_finish_mixed(TlParams p, int nmax) {
+  extern __shared__ char dyn[];
+  int* sI = reinterpret_cast<int*>(dyn);
+  float2* bvec = reinterpret_cast<float2*>(dyn + ((size_t)nmax * 4 + 15) / 16 * 16);
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const TlItem t = tl_item(p, b);
+  char* slot = p.ws + (size_t)b * p.slot_bytes;
+  const float2* W = reinterpret_cast<const float2*>(slot);
+  const int* piv = reinterpret_cast<const int*>(slot + p.lay.piv_off);
+  const int* aux = reinterpret_cast<const int*>(slot + p.lay.aux_off);
+  double2* x = reinterpret_cast<double2*>(slot + p.lay.x_off);
+  for (int s = tid; s < t.N; s += kThreads) sI[s] = p.Ilist[(size_t)t.c * p.M + s];
+  const int bad = aux[0];
+  __syncthreads();
+  const size_t item = (size_t)t.c * p.F + t.f;
+  refine_item(W, p.lay.ld, t.N, piv, p.kb, bvec, sI, x, p.Z128 + (size_t)t.f * p.M * p.M, p.M, p.P, p.port_len,
+              p.z0, p.ir_max, p.ir_tol, bad, (int)item, p.S + item * p.P * p.P, p.status + item, p.ir_iters,
+              p.fb_count, p.fb_list);
+}
+
+template <typename R, int Q>
+constexpr int tl_sb() {
+  return sizeof(R) == 8 ? (16 / Q > 0 ? 16 / Q : 1) : (32 / Q > 0 ? 32 / Q : 1);
+}
+
+template <typename R>
+hipError_t panel_variant(hipStream_t s, const TlParams& p, int K, int q) {
+  const dim3 g(p.B), blk(kThreads);
+  if (q <= 1) hipLaunchKernelGGL((k_tl_panel<R, 1, tl_sb<R, 1>()>), g, blk, 0, s, p, K);
+  else if (q <= 2) hipLaunchKernelGGL((k_tl_panel<R, 2, tl_sb<R, 2>()>), g, blk, 0, s, p, K);
+  else if (q <= 4) hipLaunchKernelGGL((k_tl_panel<R, 4, tl_sb<R, 4>()>), g, blk, 0, s, p, K);
+  else if (q <= 8) hipLaunchKernelGGL((k_tl_panel<R, 8, tl_sb<R, 8>()>), g, blk, 0, s, p, K);
+  else if (q <= 12) hipLaunchKernelGGL((k_tl_panel<R, 12, tl_sb<R, 12>()>), g, blk, 0, s, p, K);
+  else if (q <= 16) hipLaunchKernelGGL((k_tl_panel<R, 16, tl_sb<R, 16>()>), g, blk, 0, s, p, K);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+constexpr int kTrsmCols64 = 64, kTrsmCols128 = 32;
+constexpr int kTM64 = 128, kTN64 = 64, kKC64 = 32;
+constexpr int kTM128 = 128, kTN128 = 64, kKC128 = 16;
+
+}  // namespace
+
+int tl_max_active() { return 256 * 16; }
+
+hipError_t tl_gather(hipStream_t s, const TlParams& p, int nmax) {
+  const dim3 g((nmax + 15) / 16, p.B), blk(kThreads);
+  if (!p.mixed) hipLaunchKernelGGL((k_tl_gather<double2, double2>), g, blk, 0, s, p, p.Z128);
+  else if (p.Z64) hipLaunchKernelGGL((k_tl_gather<float2, float2>), g, blk, 0, s, p, p.Z64);
+  else hipLaunchKernelGGL((k_tl_gather<float2, double2>), g, blk, 0, s, p, p.Z128);
+  return hipGetLastError();
+}
+
+hipError_t tl_panel(hipStream_t s, const TlParams& p, int K, int nmax) {
+  const int q = (nmax - K + 255) / 256;
+  return p.mixed ? panel_variant<float>(s, p, K, q) : panel_variant<double>(s, p, K, q);
+}
+
+hipError_t tl_trsm(hipStream_t s, const TlParams& p, int K, int nmax) {
+  const int ncols = p.mixed ? nmax : nmax + p.P;
+  if (ncols <= K) return hipSuccess;
+  if (p.mixed) {
+    const dim3 g((ncols - K + kTrsmCols64 - 1) / kTrsmCols64, p.B), blk(kThreads);
+    hipLaunchKernelGGL((k_tl_trsm<float, kTrsmCols64>), g, blk, 0, s, p, K);
+  } else {
+    const dim3 g((ncols - K + kTrsmCols128 - 1) / kTrsmCols128, p.B), blk(kThreads);
+    hipLaunchKernelGGL((k_tl_trsm<double, kTrsmCols128>), g, blk, 0, s, p, K);
+  }
+  return hipGetLastError();
+}
+
+hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax) {
+  const int ncols = p.mixed ? nmax : nmax + p.P;
+  const int mr = nmax - K, nc = ncols - K;  // bounds of every item's trailing block
+  if (mr <= 0 || nc <= 0) return hipSuccess;
+  const int TM = p.mixed ? kTM64 : kTM128, TN = p.mixed ? kTN64 : kTN128;
+  const int tiles_m = (mr + TM - 1) / TM, tiles_n = (nc + TN - 1) / TN;
+  const int gx = (tiles_m * tiles_n + 7) / 8 * 8;  // a multiple of 8: the XCD grouping needs it
+  const dim3 g(gx, p.B), blk(kThreads);
+  if (p.mixed) hipLaunchKernelGGL((k_tl_update<float, kTM64, kTN64, kKC64>), g, blk, 0, s, p, K, tiles_m, tiles_n);
+  else hipLaunchKernelGGL((k_tl_update<double, kTM128, kTN128, kKC128>), g, blk, 0, s, p, K, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+hipError_t tl_prepare(const TlParams& p, int nmax) {
+  if (!p.mixed) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tl_finish_mixed),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)eval_mixed_lds(nmax, p.P));
+}
+
+hipError_t tl_finish(hipStream_t s, const TlParams& p, int nmax) {
+  if (p.mixed)
+    hipLaunchKernelGGL(k_tl_finish_mixed, dim3(p.B), dim3(kThreads), eval_mixed_lds(nmax, p.P), s, p, nmax);
+  else
+    hipLaunchKernelGGL(k_tl_finish_plain, dim3(p.B), dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace pxd

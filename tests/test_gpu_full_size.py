@@ -70,9 +70,9 @@ def test_stress24_full_batch_every_precision():
         assert np.all((status == 0) | (status == 1))
 
 
-def test_ceiling32_active_size_is_refused():
-    """The 32x32x3 stack's active sets (N ~ 3,000) exceed the kernels' 2,048
-    limit: the library refuses the batch instead of running it."""
+def test_active_size_above_the_tiled_limit_is_refused():
+    """The all-metal 32x32x3 map has N = M = 9,036, above the tiled LU's
+    4,096: the library refuses the batch instead of running it."""
     spec = get_spec("ceiling32")
     pb = pxd.Problem.from_spec(spec)
     ev = pxd.Evaluator()
@@ -80,8 +80,8 @@ def test_ceiling32_active_size_is_refused():
     ev.load_parent(Z, spec.freqs[:1])
     ev.load_problem(pb, spec.z0)
     ev.set_fom_paper()
-    off = np.array([0, 1], np.int32)
+    off = np.array([0, 0], np.int32)
     with pytest.raises(pxd.PxdError) as e:
-        ev.evaluate_flips(spec.base_map(), off, np.array([0], np.int32))
+        ev.evaluate_flips(np.ones(spec.n_cells, np.uint8), off, np.zeros(0, np.int32))
     assert e.value.code == pxd.ESHAPE
     ev.close()
