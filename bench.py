@@ -1,12 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the per-candidate MoM evaluation on one MI355X.
 
-Workload (default): two metal layers of 20 x 20 half-millimetre pixels in a
-lossy dielectric (eps_r 3.5, tan d 0.002), three ports, 13 vias, parent size
-M = 2371, 101 frequencies over 1-8 GHz; one step evaluates all 800
-single-flip candidates of the seeded Bernoulli(0.5) map at every frequency
-(gather, dense LU, S, FoM, argmin).  Inputs are synthetic and resident in HBM
-before timing starts; the parent fill is pre-computation and not timed.
+Headline workload (default, the largest one-GPU configuration): three metal
+layers of 32 x 32 pixels of 0.3 mm (Table I's 0.4866 mm stack, eps_r 3.66,
+tan d 0.004), three ports, parent size M = 9,036, 201 frequencies over
+0.5-10 GHz.  One step is one search step of the depth-two tree search on the
+seeded Bernoulli(0.5) map: the CNN surrogate ranks all 9,024 pair flips within
+3 x 3 neighbourhoods, and the best 32 are evaluated exactly at every frequency
+(gather of Z_A, dense LU, S, FoM, argmin).  The chosen form (complex64 LU +
+FP64 iterative refinement) is timed beside the FP64 plain path on the same
+candidates.  Inputs are synthetic and resident in HBM before timing starts;
+the parent fill (the paper's pre-computation phase) is not timed.
+
+Further legs (each its own context): the 24 x 24 x 3 stack (64 single flips,
+101 frequencies; FP64, complex64 and BF16 block-update forms), the 20 x 20 x 2
+stack with vias (all 800 single flips, 101 frequencies; path autotuned), the
+surrogate ranking at its working size and the low-rank flip evaluation.
 
 Prints one JSON line (stdout).  Progress goes to stderr.
 """
@@ -14,6 +23,8 @@ Prints one JSON line (stdout).  Progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import concurrent.futures
+import hashlib
 import json
 import os
 import sys
@@ -24,7 +35,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3, "bf16": 157.3}
+PREC = {"fp64": 0, "mixed32": 1, "bf16": 2}
 
 
 def log(msg):
@@ -38,16 +50,17 @@ def lu_flops(N, P):
     return (8.0 / 3.0) * N ** 3 + 8.0 * P * N ** 2
 
 
-KERNEL_OF = {"fp64": "k_eval_plain", "mixed32": "k_eval_mixed"}
+def kernel_name(path, mode):
+    if path == "tiled":
+        return "k_tl_update<double>" if mode == "fp64" else "k_tl_update<float>"
+    return "k_eval_plain" if mode == "fp64" else "k_eval_mixed"
 
 
 def measured_traffic(workload, kernel, items):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is none for
     this workload or the kernel sources changed since it was taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", f"k_eval_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -57,154 +70,322 @@ def measured_traffic(workload, kernel, items):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     k = rec["kernels"].get(kernel)
-    if h.hexdigest() != rec["source_sha256"] or k is None or rec["items_per_launch"] != items:
+    if h.hexdigest() != rec["source_sha256"] or k is None or rec["items_per_step"] != items:
         return None
-    return k["hbm_bytes_per_launch"]
+    return k
 
 
-def cpu_baseline(spec, gpu_S, sample_c, seconds):
-    """Time the oracle (as it stands) on a bounded sample of the same
-    workload: its own parent fill at one frequency (not timed), then Eq. 5
-    gather, LAPACK solve, S and the per-frequency FoM terms for a set of
-    candidates, repeated until `seconds` of work; scaled to evaluations/s over
-    all frequencies.  Also returns the sampled max |dS| against the GPU."""
-    from oracle import efie, fom as ofom, geometry, network, search
+# ---------------------------------------------------------------- CPU baseline (oracle)
 
-    try:
-        from threadpoolctl import threadpool_info
+def oracle_prepare(jobs):
+    """Untimed part of the CPU baseline, run in a background thread while the
+    GPU legs run: the oracle's own fill for each sampled system (the paper's
+    pre-computation phase).  jobs: (label, spec, maps, f_index, subset)."""
+    from oracle import efie, geometry, network
 
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count()
-    f_idx = int(np.argmin(np.abs(spec.freqs - 5.5e9)))
-    f = spec.freqs[f_idx]
-    st = geometry.build_structure(spec)
-    log(f"cpu baseline: oracle fill at {f / 1e9:.2f} GHz (M = {st.M})")
-    t = time.time()
-    Z = efie.fill(st, f)
-    log(f"cpu baseline: oracle fill took {time.time() - t:.1f} s")
-    base = spec.base_map()
-    off, cells = spec.flips()
-    maps = search.candidate_maps(base, off, cells)
-    pl = search.port_lengths(st)
-    dS = 0.0
-    done = 0
-    t0 = time.perf_counter()
-    while True:
-        for c in sample_c:
-            sel = st.active(maps[c])
-            rows = network.port_positions(sel, st.port_bf)
-            S = network.s_parameters(network.reduce_matrix(Z, sel), rows, pl, spec.z0)
-            ofom.rewards(S)
-            if done < len(sample_c):
-                dS = max(dS, float(np.abs(S - gpu_S[c, f_idx]).max()))
-            done += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    per_item = el / done
-    value = 1.0 / (per_item * spec.n_freq)
-    sample = (f"{len(sample_c)} candidates x 1 frequency ({f / 1e9:.2f} GHz), {done} solves in {el:.1f} s, "
-              f"scaled x{spec.n_freq} frequencies per evaluation")
-    return {"value": value, "unit": "evals/s", "cores": int(cores), "kind": "oracle", "sample": sample}, dS
-
-
-def lowrank_leg(args, pxd, spec, pb, Z, base, off, cells, results):
-    """The same batch through the low-rank flip evaluation (FP64, from the
-    cached inverse of the base map), host buffers in and out."""
-    C = len(off) - 1
-    ev = pxd.Evaluator(device=0, precision=pxd.PREC_FP64)
-    ev.load_parent(Z, spec.freqs)
-    ev.load_problem(pb, spec.z0)
-    ev.set_fom_paper()
-    Nc, idx = ev.expand(base, off, cells)
-    NB, idx_b = ev.expand(base, np.zeros(2, np.int32), np.zeros(0, np.int32))
-    bset = set(idx_b[0].tolist())
-    added = np.array([len(set(idx[c].tolist()) - bset) for c in range(C)])
-    t0 = time.perf_counter()
-    S, fom, st, am = ev.evaluate_flips_lowrank(base, off, cells)
-    first_ms = (time.perf_counter() - t0) * 1e3
-    s_first = ev.stats()
-    log(f"[lowrank] first call {first_ms:.1f} ms (base inverse {s_first['ms_base_inverse']:.1f} ms, "
-        f"N_B = {NB[0]}, {s_first['fallbacks']} dense items)")
-    t0 = time.perf_counter()
-    k_ms = []
-    for i in range(args.steps):
-        S, fom, st, am = ev.evaluate_flips_lowrank(base, off, cells)
-        k_ms.append(ev.stats()["ms_solve"])
-        log(f"[lowrank] step {i + 1}/{args.steps}: kernel {k_ms[-1]:.2f} ms")
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    stats = ev.stats()
-    ev.close()
-    # algorithmic bytes of the low-rank kernel: one pass over G (N_B^2 complex128)
-    # per four added functions, per (candidate, frequency)
-    passes = float(np.sum((added + 3) // 4)) * spec.n_freq
-    g_bytes = passes * float(NB[0]) ** 2 * 16
-    k = float(np.mean(k_ms))
-    out = {
-        "value": C / (ms / 1e3), "unit": "evals/s", "ms_per_step": ms, "kernel_ms": k,
-        "first_call_ms": first_ms, "ms_base_inverse": s_first["ms_base_inverse"],
-        "base_reused": int(stats["base_reused"]), "dense_fallback_items": int(stats["fallbacks"]),
-        "status_errors": int(np.count_nonzero(st != 0)),
-        "io": "host buffers (PCIe copies of flips and S inside the timed step)",
-        "g_stream": {"bytes_per_launch": g_bytes, "achieved_GBps": g_bytes / (k / 1e3) / 1e9,
-                     "basis": "N_B^2 x 16 B per pass, ceil(added / 4) passes per (candidate, frequency)"},
-        "traffic": measured_traffic(spec.name, "k_lowrank", C * spec.n_freq),
-    }
-    if "fp64" in results:
-        f64 = results["fp64"]
-        sc = f64["sample_c"]
-        out["max_dS_vs_fp64_plain"] = float(np.abs(S[sc] - f64["S_sample"]).max())
-        out["argmin_equal_fp64_plain"] = bool(am == f64["am"])
-        out["fom_rel_dev_vs_fp64_plain"] = float(np.max(np.abs(fom - f64["fom"]) / f64["fom"]))
-        out["speedup_vs_fp64_plain"] = out["value"] / f64["value"]
+    out = []
+    for label, spec, maps, fi, subset in jobs:
+        t = time.time()
+        st = geometry.build_structure(spec)
+        if subset:  # the union of the sampled candidates' active sets only
+            union = np.zeros(st.M, bool)
+            for m in maps:
+                union |= st.active(m)
+            idx = network.support(union)
+        else:
+            idx = np.arange(st.M)
+        Z = efie.fill(st, spec.freqs[fi], bf_subset=idx)
+        out.append((label, spec, st, maps, fi, idx, Z))
+        log(f"cpu baseline: oracle fill for {label} ({len(idx)} functions) took {time.time() - t:.0f} s")
     return out
 
 
-def surrogate_leg(args, pxd, spec, pb, torch):
-    """Ranking by the CNN surrogate at its working size: a 3 x 24 x 24 map
-    (channels 32-64, hidden 256, BF16 products) scored on the workload's 101
-    frequencies with its FoM table; every single flip and every pair of
-    cells, then the top 32.  Random-init weights (throughput only)."""
+def oracle_time(prepared, seconds, threads=None):
+    """Time the oracle's per-candidate work (Eq. 5 gather, LAPACK solve, S by
+    Eqs. 6-7, Eq. 9 terms) on each prepared sample for about `seconds`,
+    scaled to evaluations/s over all the workload's frequencies."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import fom as ofom
+    from oracle import network, search
+
+    res = {}
+    with threadpool_limits(limits=threads):
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        for label, spec, st, maps, fi, idx, Z in prepared:
+            pos = -np.ones(st.M, np.int64)
+            pos[idx] = np.arange(len(idx))
+            pl = search.port_lengths(st)
+            done, t0 = 0, time.perf_counter()
+            while True:
+                for m in maps:
+                    sel = st.active(m)
+                    rows = pos[network.support(sel)]
+                    Za = Z[np.ix_(rows, rows)]
+                    S = network.s_parameters(Za, network.port_positions(sel, st.port_bf), pl, spec.z0)
+                    ofom.rewards(S)
+                    done += 1
+                el = time.perf_counter() - t0
+                if el >= seconds / len(prepared):
+                    break
+            res[label] = {"value": 1.0 / (el / done * spec.n_freq), "unit": "evals/s", "cores": int(cores),
+                          "kind": "oracle",
+                          "sample": f"{len(maps)} candidates x 1 frequency ({spec.freqs[fi] / 1e9:.3f} GHz), "
+                                    f"{done} solves in {el:.1f} s, scaled x{spec.n_freq} frequencies per evaluation"}
+    return res
+
+
+# ---------------------------------------------------------------- GPU legs
+
+def _events(torch, stream):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    return e0, e1
+
+
+def headline_leg(args, pxd, torch, spec, modes):
+    """Surrogate-prefiltered search step of the 32 x 32 x 3 workload."""
     dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    pb = pxd.Problem.from_spec(spec)
+    freqs = spec.freqs
+    base = spec.base_map()
+    off, cells = spec.flips()
+    C_all, k = len(off) - 1, args.top_k
+    P = len(spec.ports)
+    pairs = cells.reshape(C_all, 2)
+    t_base, t_off, t_cells = (torch.from_numpy(a).to(dev) for a in (base, off, cells))
+    sub_off = torch.from_numpy(np.arange(0, 2 * k + 1, 2, dtype=np.int32)).to(dev)
+    sub_cells = torch.zeros(2 * k, dtype=torch.int32, device=dev)
+    fp = torch.empty(C_all, dtype=torch.float64, device=dev)
+    top = torch.empty(k, dtype=torch.int32, device=dev)
+    sur = pxd.Surrogate(spec.n_layers, spec.ny, spec.nx, freqs, freqs[0], freqs[-1], precision=pxd.SUR_BF16,
+                        max_batch=2048)
+    sur.init_params(17)
+    out = {"candidates_ranked": C_all, "top_k": k}
+    for mode in modes:
+        ev = pxd.Evaluator(device=0, precision=PREC[mode], ir_max_iter=args.ir_max)
+        ev.load_problem(pb, spec.z0)
+        torch.cuda.synchronize()
+        t = time.time()
+        ev.load_parent_problem(pb, freqs)
+        fill_s = time.time() - t
+        ev.set_fom_paper()
+        log(f"[headline {mode}] parent filled on the GPU: M = {pb.M}, {len(freqs)} frequencies, "
+            f"{len(freqs) * pb.M * pb.M * 16 / 1e9:.0f} GB complex128, {fill_s:.1f} s")
+        S_out = torch.empty((k, len(freqs), P, P, 2), dtype=torch.float64, device=dev)
+        fom_out = torch.empty(k, dtype=torch.float64, device=dev)
+        st_out = torch.empty(k, dtype=torch.int32, device=dev)
+        am_out = torch.empty(1, dtype=torch.int32, device=dev)
+        rank_ms = []
+
+        def step():
+            r0, r1 = _events(torch, stream)
+            r0.record(stream)
+            sur.rank(ev, t_base, t_off, t_cells, k, fp, top, stream)
+            r1.record(stream)
+            sel = top.cpu().numpy()  # the surrogate's best k (synchronises)
+            rank_ms.append(r0.elapsed_time(r1))
+            sub_cells.copy_(torch.from_numpy(np.ascontiguousarray(pairs[sel].reshape(-1))))
+            ev.evaluate_flips_device(stream, t_base, sub_off, sub_cells, S_out, fom_out, st_out, am_out)
+            return sel
+
+        n_warm, n_steps = (args.warmup, args.steps) if mode == modes[-1] else (0, 1)
+        ev.set_profiling(True)
+        for i in range(n_warm):
+            step()
+            torch.cuda.synchronize()
+            log(f"[headline {mode}] warmup {i + 1}/{n_warm}")
+        torch.cuda.synchronize()
+        rank_ms.clear()
+        stats = []
+        e0, e1 = _events(torch, stream)
+        e0.record(stream)
+        for i in range(n_steps):
+            sel = step()
+            stats.append(ev.stats())
+            s = stats[-1]
+            log(f"[headline {mode}] step {i + 1}/{n_steps}: solve {s['ms_solve']:.0f} ms, fallback "
+                f"{s['ms_fallback']:.0f} ms ({s['fallbacks']} items), refinement steps {s['ir_iterations']}, "
+                f"trailing updates {s['ms_update']:.0f} ms in {s['update_launches']} launches "
+                f"({s['update_gflop'] / max(s['ms_update'], 1e-9):.1f} TFLOP/s)")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n_steps
+        sub_o = np.arange(0, 2 * k + 1, 2, dtype=np.int32)
+        N, _ = ev.expand(base, sub_o, pairs[sel].reshape(-1).astype(np.int32))
+        s = stats[-1]
+        flops = float(lu_flops(N, P).sum() * len(freqs))
+        if mode != "fp64":
+            flops += 16.0 * P * float(np.mean(N.astype(np.float64) ** 2)) * s["ir_iterations"]
+        upd_ms = float(np.mean([x["ms_update"] for x in stats]))
+        upd_gflop = float(np.mean([x["update_gflop"] for x in stats]))
+        upd_n = int(stats[-1]["update_launches"])
+        out[mode] = {
+            "value": k / (ms / 1e3), "ms_per_step": ms, "steps": n_steps, "warmup": n_warm,
+            "solve_ms": float(np.mean([x["ms_solve"] for x in stats])),
+            "fallback_ms": float(np.mean([x["ms_fallback"] for x in stats])),
+            "rank_ms": float(np.mean(rank_ms)), "fill_s": fill_s,
+            "fallbacks": int(s["fallbacks"]), "ir_steps": int(s["ir_iterations"]), "N": N,
+            "lu_tflops_step": flops / (ms / 1e3) / 1e12,
+            "update": {"kernel": kernel_name("tiled", mode), "launches_per_step": upd_n,
+                       "ms_per_step": upd_ms, "gflop_per_step": upd_gflop,
+                       "achieved_tflops": upd_gflop / upd_ms, "avg_launch_us": 1e3 * upd_ms / max(upd_n, 1),
+                       "gflop_per_launch": upd_gflop / max(upd_n, 1)},
+            "status_errors": int(np.count_nonzero(st_out.cpu().numpy() < 0)),
+            "fom": fom_out.cpu().numpy(), "am": int(am_out.cpu().numpy()[0]), "sel": sel,
+            "S": torch.view_as_complex(S_out.contiguous()).cpu().numpy(),
+        }
+        ev.close()
+        del S_out
+        torch.cuda.empty_cache()
+    sur.close()
+    return out
+
+
+def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False):
+    """Single-flip candidates of a workload at every frequency, device
+    buffers, one evaluator call per step."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    pb = pxd.Problem.from_spec(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    off, cells = off[:n_cand + 1], cells[:off[n_cand]]
+    P = len(spec.ports)
+    t_base, t_off, t_cells = (torch.from_numpy(a).to(dev) for a in (base, off, cells))
+    out = {"candidates": n_cand, "frequencies": spec.n_freq}
+    for mode in modes:
+        ev = pxd.Evaluator(device=0, precision=PREC[mode], ir_max_iter=args.ir_max, half_subpanel=1)
+        ev.load_problem(pb, spec.z0)
+        ev.load_parent_problem(pb, spec.freqs)
+        ev.set_fom_paper()
+        tuned = None
+        if tune:
+            nt = min(n_cand, 96)
+            rep = ev.autotune(base, off[:nt + 1], cells[:off[nt]], n_reps=1)
+            tuned = [(r["lu_path"], r["tile_kb"], r["wg_per_cu"], r["schedule"], round(r["ms"], 1)) for r in rep]
+            log(f"[{label} {mode}] autotuned on {nt} candidates: {tuned[:4]}")
+        S_out = torch.empty((n_cand, spec.n_freq, P, P, 2), dtype=torch.float64, device=dev)
+        fom_out = torch.empty(n_cand, dtype=torch.float64, device=dev)
+        st_out = torch.empty(n_cand, dtype=torch.int32, device=dev)
+        am_out = torch.empty(1, dtype=torch.int32, device=dev)
+
+        def step():
+            ev.evaluate_flips_device(stream, t_base, t_off, t_cells, S_out, fom_out, st_out, am_out)
+
+        step()
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, stream)
+        e0.record(stream)
+        stats = []
+        for i in range(args.leg_steps):
+            step()
+            stats.append(ev.stats())
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.leg_steps
+        s = stats[-1]
+        N, _ = ev.expand(base, off, cells)
+        flops = float(lu_flops(N, P).sum() * spec.n_freq)
+        out[mode] = {"value": n_cand / (ms / 1e3), "ms_per_step": ms, "solve_ms": s["ms_solve"],
+                     "fallback_ms": s["ms_fallback"], "fallbacks": int(s["fallbacks"]),
+                     "ir_steps": int(s["ir_iterations"]), "active_size": [int(N.min()), int(N.max())],
+                     "lu_tflops_step": flops / (ms / 1e3) / 1e12, "tuned": tuned,
+                     "status_errors": int(np.count_nonzero(st_out.cpu().numpy() < 0)),
+                     "fom": fom_out.cpu().numpy(), "am": int(am_out.cpu().numpy()[0]),
+                     "S": torch.view_as_complex(S_out.contiguous()).cpu().numpy()}
+        log(f"[{label} {mode}] {out[mode]['value']:.1f} evals/s ({ms:.0f} ms per step, N {N.min()}-{N.max()}, "
+            f"{s['fallbacks']} to FP64, {s['ir_iterations']} refinement steps)")
+        ev.close()
+        del S_out
+        torch.cuda.empty_cache()
+    ref = out.get("fp64")
+    for mode in modes:
+        if mode != "fp64" and ref is not None:
+            r = out[mode]
+            r["max_dS_vs_fp64_plain"] = float(np.abs(r["S"] - ref["S"]).max())
+            r["argmin_equal_fp64_plain"] = bool(r["am"] == ref["am"])
+            r["speedup_vs_fp64_plain"] = r["value"] / ref["value"]
+    for mode in modes:
+        for key in ("S", "fom"):
+            out[mode].pop(key, None)
+    return out
+
+
+def lowrank_leg(args, pxd, spec):
+    """All single flips of the 20 x 20 x 2 map through the low-rank flip
+    evaluation (FP64, from the cached inverse of the base map), host buffers."""
+    pb = pxd.Problem.from_spec(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    C = len(off) - 1
+    ev = pxd.Evaluator(device=0, precision=pxd.PREC_FP64)
+    ev.load_problem(pb, spec.z0)
+    ev.load_parent_problem(pb, spec.freqs)
+    ev.set_fom_paper()
+    t0 = time.perf_counter()
+    ev.evaluate_flips_lowrank(base, off, cells, want_S=False)
+    first_ms = (time.perf_counter() - t0) * 1e3
+    s_first = ev.stats()
+    t0 = time.perf_counter()
+    k_ms = []
+    for i in range(args.leg_steps):
+        ev.evaluate_flips_lowrank(base, off, cells, want_S=False)
+        k_ms.append(ev.stats()["ms_solve"])
+    ms = (time.perf_counter() - t0) * 1e3 / args.leg_steps
+    st = ev.stats()
+    ev.close()
+    log(f"[lowrank] {C / (ms / 1e3):.0f} evals/s ({ms:.1f} ms per step, kernel {np.mean(k_ms):.1f} ms, base inverse "
+        f"{s_first['ms_base_inverse']:.0f} ms once)")
+    return {"value": C / (ms / 1e3), "unit": "evals/s", "ms_per_step": ms, "kernel_ms": float(np.mean(k_ms)),
+            "first_call_ms": first_ms, "ms_base_inverse": s_first["ms_base_inverse"],
+            "base_reused": int(st["base_reused"]), "dense_fallback_items": int(st["fallbacks"]),
+            "io": "host buffers (flips up, FoM down inside the timed step)"}
+
+
+def surrogate_leg(args, pxd, spec, torch):
+    """Ranking by the CNN surrogate at its working size: a 3 x 24 x 24 map
+    (channels 32-64, hidden 256, BF16 products) scored on 101 frequencies with
+    the context's FoM table; every single flip and every pair of cells, then
+    the top 32.  Random-init weights (throughput only)."""
+    dev = torch.device("cuda:0")
+    pb = pxd.Problem.from_spec(spec)
     ev = pxd.Evaluator(device=0)
     ev.load_problem(pb, spec.z0)
     ev.load_parent_problem(pb, spec.freqs)
     ev.set_fom_paper()
-    L, ny, nx = 3, 24, 24
+    L, ny, nx = spec.n_layers, spec.ny, spec.nx
     n = L * ny * nx
-    sur = pxd.Surrogate(L, ny, nx, spec.freqs, spec.freqs[0], spec.freqs[-1], precision=pxd.SUR_BF16,
-                        max_batch=2048)
+    sur = pxd.Surrogate(L, ny, nx, spec.freqs, spec.freqs[0], spec.freqs[-1], precision=pxd.SUR_BF16, max_batch=2048)
     sur.init_params(17)
     iu, ju = np.triu_indices(n, 1)
     C = n + len(iu)
     off = np.concatenate([np.arange(n + 1), n + 2 * np.arange(1, len(iu) + 1)]).astype(np.int32)
     cells = np.concatenate([np.arange(n), np.stack([iu, ju], 1).ravel()]).astype(np.int32)
-    base = (np.arange(n) % 2).astype(np.uint8)
+    base = spec.base_map()
     t_base, t_off, t_cells = (torch.from_numpy(a).to(dev) for a in (base, off, cells))
     fp = torch.empty(C, dtype=torch.float64, device=dev)
     top = torch.empty(32, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    sur.rank(ev, t_base, t_off, t_cells, 32, fp, top, stream)  # warm-up
+    sur.rank(ev, t_base, t_off, t_cells, 32, fp, top, stream)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = _events(torch, stream)
     e0.record(stream)
     sur.rank(ev, t_base, t_off, t_cells, 32, fp, top, stream)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     ok = bool(torch.isfinite(fp).all().item()) and int(top.min().item()) >= 0
-    log(f"[surrogate] ranked {C:,} candidates (3x24x24 map, 101 frequencies) in {ms:.0f} ms, top-32 valid {ok}")
-    # trunk work per map: four 3x3 convolutions; head: two products per (map, frequency)
-    ch = (3, 32, 32, 64, 64)
+    ch = (L, 32, 32, 64, 64)
     px = (ny * nx, ny * nx, ny * nx // 4, ny * nx // 4)
     trunk = sum(2 * 9 * ch[i] * ch[i + 1] * px[i] for i in range(4))
     feat = 64 * (ny // 4) * (nx // 4)
-    flops = C * (trunk + 2 * feat * 256 + len(spec.freqs) * 2 * 256 * 9)
+    flops = C * (trunk + 2 * feat * 256 + spec.n_freq * 2 * 256 * 9)
     sur.close()
     ev.close()
+    log(f"[surrogate] ranked {C:,} candidates in {ms:.0f} ms ({flops / (ms / 1e3) / 1e12:.1f} TFLOP/s)")
     return {"value": C / (ms / 1e3), "unit": "maps/s", "ms": ms, "candidates": C,
-            "workload": "every single flip and cell pair of a 3x24x24 map, 101 frequencies, top 32",
+            "workload": f"every single flip and cell pair of a {L}x{ny}x{nx} map, {spec.n_freq} frequencies, top 32",
             "precision": "bf16 products, fp32 accumulation", "weights": "random init (throughput only)",
             "flops_per_call": flops, "achieved_TFLOPs": flops / (ms / 1e3) / 1e12, "peak_TFLOPs": 2500.0,
             "top_valid": ok}
@@ -213,18 +394,16 @@ def surrogate_leg(args, pxd, spec, pb, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched20")
-    ap.add_argument("--precision", default="both", choices=sorted(PEAK_TFLOPS) + ["both"])
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="ceiling32")
+    ap.add_argument("--top-k", type=int, default=32)
+    ap.add_argument("--ir-max", type=int, default=10)
+    ap.add_argument("--leg-steps", type=int, default=1)
+    ap.add_argument("--legs", default="stress24,batched20,surrogate,lowrank",
+                    help="comma list of extra legs (stress24, batched20, surrogate, lowrank) or 'none'")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank flip evaluation leg")
-    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate ranking leg")
-    ap.add_argument("--fill-threads", type=int, default=16)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="first copy 1 GiB device to device, a reference kernel of known traffic for "
-                         "byte counters (FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (the path shards by frequency "
@@ -236,175 +415,135 @@ def main():
     from paper_2412_17617_amd import pxd
     from synth import get_spec
 
-    if args.copy_calibration:
-        src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")
-        torch.cuda.synchronize()
-        dst = src.clone()  # reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        del src, dst
-        log("copy calibration: 1 GiB device-to-device copy done")
-
+    legs = [] if args.legs == "none" else [x for x in args.legs.split(",") if x]
     spec = get_spec(args.workload)
-    freqs = spec.freqs
     log(f"workload {spec.name}: {spec.n_layers} layers {spec.nx}x{spec.ny}, {spec.n_freq} frequencies")
-    pb = pxd.Problem.from_spec(spec)
-    t = time.time()
-    Z = pb.fill(freqs, n_threads=args.fill_threads)
-    host_fill_s = time.time() - t
-    log(f"parent fill (host, {args.fill_threads} threads): M = {pb.M}, {host_fill_s:.1f} s")
-    dev = torch.device("cuda:0")
-    Zd = torch.empty((spec.n_freq, pb.M, pb.M), dtype=torch.complex128, device=dev)
-    torch.cuda.synchronize()
-    t = time.time()
-    pb.fill_device(freqs, Zd)
-    torch.cuda.synchronize()
-    gpu_fill_s = time.time() - t
-    chk = list(range(0, spec.n_freq, max(1, spec.n_freq // 4)))
-    fill_dev = float(max(np.abs(Zd[f].cpu().numpy() - Z[f]).max() / np.abs(Z[f]).max() for f in chk))
-    del Zd
-    log(f"parent fill (GPU): {gpu_fill_s * 1e3:.0f} ms, max |dZ| / max |Z| vs host fill {fill_dev:.1e}")
-    parent_fill = {"gpu_s": gpu_fill_s, "host_s": host_fill_s, "host_threads": args.fill_threads,
-                   "speedup": host_fill_s / gpu_fill_s, "max_rel_dZ_vs_host": fill_dev,
-                   "frequencies": spec.n_freq, "M": pb.M}
-    base = spec.base_map()
-    off, cells = spec.flips()
-    C = len(off) - 1
-    P = len(spec.ports)
-    t_base = torch.from_numpy(base).to(dev)
-    t_off = torch.from_numpy(off).to(dev)
-    t_cells = torch.from_numpy(cells).to(dev)
-    stream = torch.cuda.current_stream()
-    modes = ["fp64", "mixed32"] if args.precision == "both" else [args.precision]
-    results = {}
-    for mode in modes:
-        prec = pxd.PREC_FP64 if mode == "fp64" else pxd.PREC_MIXED32
-        # full-width register sub-panel; workgroups per CU and item order autotuned
-        ev = pxd.Evaluator(device=0, precision=prec, half_subpanel=1)
-        ev.load_parent(Z, freqs)
-        ev.load_problem(pb, spec.z0)
-        ev.set_fom_paper()
-        n_tune = min(C, 96)
-        tune = ev.autotune(base, off[:n_tune + 1], cells[:off[n_tune]], n_reps=1)
-        log(f"[{mode}] autotuned on {n_tune} candidates: " +
-            ", ".join(f"wg/CU {t['wg_per_cu']} order {t['schedule']} {t['ms']:.0f} ms" for t in tune))
-        S_out = torch.empty((C, spec.n_freq, P, P, 2), dtype=torch.float64, device=dev)
-        fom_out = torch.empty(C, dtype=torch.float64, device=dev)
-        st_out = torch.empty(C, dtype=torch.int32, device=dev)
-        am_out = torch.empty(1, dtype=torch.int32, device=dev)
-        N, _ = ev.expand(base, off, cells)
-        flops_per_launch = float(lu_flops(N, P).sum() * spec.n_freq)
-        log(f"[{mode}] candidates {C}, active size {N.min()}..{N.max()}, {flops_per_launch / 1e12:.1f} TFLOP per step")
 
-        def step():
-            ev.evaluate_flips_device(stream, t_base, t_off, t_cells, S_out, fom_out, st_out, am_out)
+    # the CPU baseline's oracle fills (untimed) run beside the GPU legs
+    pool = concurrent.futures.ThreadPoolExecutor(1)
+    prep = None
+    if not args.no_cpu_baseline:
+        from oracle import search
 
-        for i in range(args.warmup):
-            step()
-            torch.cuda.synchronize()
-            log(f"[{mode}] warmup {i + 1}/{args.warmup}")
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        kernel_ms, stats = [], []
-        e0.record(stream)
-        for i in range(args.steps):
-            step()
-            stats.append(ev.stats())
-            kernel_ms.append(stats[-1]["ms_solve"])
-            log(f"[{mode}] step {i + 1}/{args.steps}: evaluator kernel {kernel_ms[-1]:.1f} ms, "
-                f"fallback {stats[-1]['ms_fallback']:.1f} ms ({stats[-1]['fallbacks']} items), "
-                f"refinement steps {stats[-1]['ir_iterations']}")
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        k_ms = float(np.mean(kernel_ms))
-        if mode == "mixed32":  # refinement: residual and correction solve, 16 P N^2 per step
-            flops_per_launch += 16.0 * P * float(np.mean(N.astype(np.float64) ** 2)) * stats[-1]["ir_iterations"]
-        achieved = flops_per_launch / (k_ms / 1e3) / 1e12
-        results[mode] = {
-            "value": C / (ms / 1e3), "ms_per_step": ms, "kernel_ms": k_ms, "achieved": achieved,
-            "peak": PEAK_TFLOPS[mode], "N": N, "fallbacks": int(stats[-1]["fallbacks"]),
-            "ir_steps": int(stats[-1]["ir_iterations"]), "status_nonzero": int(np.count_nonzero(
-                (st_out.cpu().numpy() != 0) & (st_out.cpu().numpy() != 1))),
-            "fom": fom_out.cpu().numpy(), "am": int(am_out.cpu().numpy()[0]),
-            "tuned": {"wg_per_cu": tune[0]["wg_per_cu"], "schedule": tune[0]["schedule"], "half_subpanel": 1,
-                      "tried": [(t["wg_per_cu"], t["schedule"], round(t["ms"], 1)) for t in tune],
-                      "batch": f"first {n_tune} candidates"},
-            "S_sample": None,
-        }
-        sample_c = list(range(0, C, max(1, C // 16)))[:16]
-        results[mode]["sample_c"] = sample_c
-        results[mode]["S_sample"] = torch.view_as_complex(S_out[sample_c].contiguous()).cpu().numpy()
-        ev.close()
-        del S_out
-    lowrank = None if args.no_lowrank else lowrank_leg(args, pxd, spec, pb, Z, base, off, cells, results)
-    surrogate = None if args.no_surrogate else surrogate_leg(args, pxd, spec, pb, torch)
-    del Z
-    chosen = "mixed32" if "mixed32" in results else modes[0]
-    r = results[chosen]
+        jobs = []
+        base = spec.base_map()
+        off, cells = spec.flips()
+        jobs.append(("headline", spec, search.candidate_maps(base, off[:2], cells[:off[1]]),
+                     int(np.argmin(np.abs(spec.freqs - 5.5e9))), True))
+        for name, nc in (("stress24", 2), ("batched20", 8)):
+            s2 = get_spec(name)
+            b2 = s2.base_map()
+            o2, c2 = s2.flips()
+            jobs.append((name, s2, search.candidate_maps(b2, o2[:nc + 1], c2[:o2[nc]]),
+                         int(np.argmin(np.abs(s2.freqs - 5.5e9))), name != "batched20"))
+        prep = pool.submit(oracle_prepare, jobs)
+
+    modes = ["fp64", "mixed32"]
+    head = headline_leg(args, pxd, torch, spec, modes)
+    extra = {}
+    if "stress24" in legs:
+        extra["stress24"] = batch_leg(args, pxd, torch, get_spec("stress24"), 64, ["fp64", "mixed32", "bf16"],
+                                      "stress24")
+    if "batched20" in legs:
+        extra["batched20"] = batch_leg(args, pxd, torch, get_spec("batched20"), 800, ["fp64", "mixed32"],
+                                       "batched20", tune=True)
+    if "surrogate" in legs:
+        extra["surrogate"] = surrogate_leg(args, pxd, get_spec("stress24"), torch)
+    if "lowrank" in legs:
+        extra["lowrank"] = lowrank_leg(args, pxd, get_spec("batched20"))
+
+    chosen = "mixed32"
+    r, f64 = head[chosen], head["fp64"]
     N = r["N"]
+    upd = r["update"]
     out = {
         "metric": "pixel-map evals/sec (all freqs, S+FoM) vs FP64 plain, at max |dS|<=1e-4",
         "value": r["value"],
         "unit": "evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": r["steps"],
+        "warmup": r["warmup"],
         "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if chosen == "fp64" else "f32+f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{spec.name}: {spec.n_layers} layers {spec.nx}x{spec.ny} pixels, M={pb.M}, "
-                        f"{spec.n_freq} freqs {spec.f_lo / 1e9:g}-{spec.f_hi / 1e9:g} GHz, {C} single flips",
-            "precision": chosen,
-            "candidates": C,
+            "workload": f"{spec.name}: {spec.n_layers} layers {spec.nx}x{spec.ny} pixels, M={pb_M(pxd, spec)}, "
+                        f"{spec.n_freq} freqs {spec.f_lo / 1e9:g}-{spec.f_hi / 1e9:g} GHz; one search step: "
+                        f"surrogate ranks {head['candidates_ranked']} 3x3 pair flips, top {head['top_k']} "
+                        f"evaluated exactly",
+            "precision": "complex64 LU + FP64 refinement (FP64 fallback)",
+            "candidates_per_step": head["top_k"],
             "frequencies": spec.n_freq,
             "active_size": [int(N.min()), int(N.max())],
-            "status_errors": r["status_nonzero"],
+            "lu_path": "tiled",
+            "status_errors": r["status_errors"],
             "fallback_items": r["fallbacks"],
             "refinement_steps": r["ir_steps"],
-            "launch": r["tuned"],
+            "surrogate_rank_ms": r["rank_ms"],
+            "surrogate_weights": "random init (the prefilter's throughput, not its ranking quality)",
+            "max_dS_vs_fp64_plain": float(np.abs(r["S"] - f64["S"]).max()),
+            "argmin_equal_fp64_plain": bool(r["am"] == f64["am"]),
+            "fom_rel_dev_vs_fp64_plain": float(np.max(np.abs(r["fom"] - f64["fom"]) / f64["fom"])),
+            "same_candidates_as_fp64_plain": bool(np.array_equal(r["sel"], f64["sel"])),
         },
         "roofline": {
             "bound": "mfma",
-            "achieved": r["achieved"],
-            "peak": r["peak"],
+            "achieved": upd["achieved_tflops"],
+            "peak": PEAK_TFLOPS[chosen],
             "unit": "TFLOP/s",
-            "frac": r["achieved"] / r["peak"],
+            "frac": upd["achieved_tflops"] / PEAK_TFLOPS[chosen],
             "traffic": None,
-            "kernel": KERNEL_OF[chosen],
-            "kernel_ms": r["kernel_ms"],
+            "kernel": upd["kernel"],
+            "launches_per_step": upd["launches_per_step"],
+            "avg_launch_us": upd["avg_launch_us"],
+            "gflop_per_launch": upd["gflop_per_launch"],
+            "basis": "algorithmic 8 kb (N - Kend)(ncols - Kend) flops per item and block column, summed over the "
+                     "step's trailing-update launches, / their summed duration (HIP event pair around each launch "
+                     "on the evaluation stream)",
         },
+        "step_breakdown_ms": {"solve": r["solve_ms"], "fp64_fallback": r["fallback_ms"],
+                              "trailing_updates": upd["ms_per_step"], "surrogate_rank": r["rank_ms"]},
+        "lu_tflops_whole_step": r["lu_tflops_step"],
+        "fp64_plain": {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
+                       "update_achieved_tflops": f64["update"]["achieved_tflops"],
+                       "update_frac": f64["update"]["achieved_tflops"] / PEAK_TFLOPS["fp64"],
+                       "lu_tflops_whole_step": f64["lu_tflops_step"], "steps": f64["steps"]},
+        "speedup_vs_fp64_plain": r["value"] / f64["value"],
+        "parent_fill_gpu_s": r["fill_s"],
     }
-    traffic = measured_traffic(spec.name, KERNEL_OF[chosen], C * spec.n_freq)
-    if traffic is not None:
-        out["roofline"]["traffic"] = traffic
-        out["roofline"]["traffic_unit"] = "bytes/launch"
-        out["roofline"]["traffic_TBps"] = traffic / (r["kernel_ms"] / 1e3) / 1e12
-    if "fp64" in results and chosen != "fp64":
-        f64 = results["fp64"]
-        out["fp64_plain"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"], "kernel_ms": f64["kernel_ms"],
-                             "roofline_frac": f64["achieved"] / f64["peak"], "achieved_tflops": f64["achieved"],
-                             "traffic": measured_traffic(spec.name, KERNEL_OF["fp64"], C * spec.n_freq)}
-        out["speedup_vs_fp64_plain"] = r["value"] / f64["value"]
-        out["config"]["max_dS_vs_fp64_plain"] = float(np.abs(r["S_sample"] - f64["S_sample"]).max())
-        out["config"]["argmin_equal_fp64_plain"] = bool(r["am"] == f64["am"])
-        out["config"]["fom_rel_dev_vs_fp64_plain"] = float(np.max(np.abs(r["fom"] - f64["fom"]) / f64["fom"]))
-    out["parent_fill"] = parent_fill
-    if lowrank is not None:
-        out["lowrank"] = lowrank
-    if surrogate is not None:
-        out["surrogate"] = surrogate
-    if not args.no_cpu_baseline:
-        sample_c = r["sample_c"]
-        S_full = np.zeros((C,) + r["S_sample"].shape[1:], np.complex128)
-        S_full[sample_c] = r["S_sample"]
-        cb, dS = cpu_baseline(spec, S_full, sample_c, args.cpu_seconds)
-        out["cpu_baseline"] = cb
-        out["config"]["max_dS_vs_oracle_sample"] = dS
+    tr = measured_traffic(spec.name, upd["kernel"], head["top_k"] * spec.n_freq)
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
+        out["roofline"]["traffic_unit"] = "bytes/launch (average)"
+    out.update(extra)
+    if prep is not None:
+        prepared = prep.result()
+        cb = oracle_time(prepared, args.cpu_seconds)
+        cb1 = oracle_time(prepared[:1], args.cpu_seconds / 3, threads=1)
+        import platform
+
+        model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+        out["cpu_baseline"] = dict(cb["headline"])
+        out["cpu_baseline"].update({"nproc": os.cpu_count(), "cpu_model": model, "machine": platform.machine(),
+                                    "one_thread": cb1["headline"],
+                                    "other_workloads": {k: v for k, v in cb.items() if k != "headline"}})
+    pool.shutdown()
     print(json.dumps(out), flush=True)
+
+
+def pb_M(pxd, spec):
+    return pxd.Problem.from_spec(spec).M
 
 
 if __name__ == "__main__":

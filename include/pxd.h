@@ -178,7 +178,10 @@ typedef struct pxd_stats {
   double ms_expand, ms_solve, ms_fallback, ms_fom; /* stage times of the last call (events) */
   double ms_base_inverse; /* low-rank calls: time of the base-map inverse (0 if reused) */
   int32_t base_reused;    /* low-rank calls: 1 if the cached base inverse served the call */
-  int32_t reserved;
+  int32_t update_launches; /* tiled path with profiling on: trailing-update launches of the last call */
+  double ms_update;       /* ... their summed duration (an event pair around each launch) */
+  double update_gflop;    /* ... their algorithmic work: 8 kb (N - Kend)(ncols - Kend) real flops per item
+                             and block column (complex multiply-add = 8 flops) */
 } pxd_stats;
 
 int pxd_create(const pxd_options* opt, pxd_ctx** out);
@@ -186,7 +189,10 @@ void pxd_destroy(pxd_ctx* ctx);
 const char* pxd_last_error(const pxd_ctx* ctx); /* ctx may be NULL: thread-local last error */
 
 /* Parent matrices: F x M x M complex128 row-major host array, frequencies in Hz.
- * The library keeps a device copy (and a complex64 copy in the mixed modes). */
+ * The library keeps a device copy and, in the mixed modes, a complex64 copy
+ * when that fits beside it with 8 GiB of device memory to spare; without the
+ * copy the mixed modes round the complex128 parent as they gather and use the
+ * tiled LU. */
 int pxd_load_parent(pxd_ctx* ctx, int32_t M, int32_t F, const double* freqs_hz, const double* Z);
 /* Same, with the parent filled on the context's device by
  * pxd_problem_fill_device straight into the context's copy (no host matrix). */
@@ -259,6 +265,10 @@ int pxd_expand(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int3
 int pxd_gather(pxd_ctx* ctx, int32_t f, int32_t N, const int32_t* idx, double* ZA_out);
 
 int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out);
+/* Profiling of the tiled path: when on, every trailing-update launch is
+ * bracketed by a pair of HIP events on the call's stream and its algorithmic
+ * work is counted (pxd_stats.update_*); off by default. */
+int pxd_set_profiling(pxd_ctx* ctx, int32_t on);
 
 /* The verdict the mixed-precision kernels take after refinement step `iters`
  * (1-based) of an item, exposed so that the rule can be checked on the host.
@@ -285,18 +295,23 @@ int pxd_evaluate_maps_device(pxd_ctx* ctx, void* stream, int32_t n_maps, const u
 
 /* One configuration tried by pxd_autotune and its measured evaluator time. */
 typedef struct pxd_tune_entry {
-  int32_t rows_per_thread; /* size class Q: active sizes up to 256 Q */
-  int32_t wg_per_cu, half_subpanel, schedule;
+  int32_t rows_per_thread; /* size class Q: active sizes up to 256 Q (Q = 1, 2, 4, 8, 16) */
+  int32_t wg_per_cu, half_subpanel, schedule; /* persistent path (wg_per_cu, half_subpanel 0 for tiled) */
+  int32_t lu_path;         /* PXD_PATH_PERSISTENT or PXD_PATH_TILED */
+  int32_t tile_kb;         /* tiled path: block-column width */
   double ms;               /* evaluator time (solve + fallback), best of n_reps */
 } pxd_tune_entry;
 
-/* Time every configuration (workgroups per CU x sub-panel width x item order)
- * on this batch (host buffers, as pxd_evaluate_flips), n_reps times each, and
- * keep the fastest for the batch's precision and size class; later calls
- * whose options say "tuned" use it.  A choice the context's options fix
- * (wg_per_cu > 0, half_subpanel 1 or 2, schedule not AUTO) is not searched.  report (may be NULL) receives up to
- * max_report entries, *n_report the number written; the chosen one is
- * report[0]. */
+/* Time every configuration on this batch (host buffers, as
+ * pxd_evaluate_flips), n_reps times each, and keep the fastest for the
+ * batch's precision and size class; later calls whose options say "tuned"
+ * use it.  Configurations: the persistent path (active sizes up to 2,048;
+ * workgroups per CU 1 or 2 x register sub-panel full or half width x item
+ * order) and the tiled path (block columns of 64 or 128 x item order).  A
+ * choice the context's options fix (lu_path, tile_kb 64/128, wg_per_cu > 0,
+ * half_subpanel 1 or 2, schedule not AUTO) is not searched.  report (may be
+ * NULL) receives up to max_report entries, *n_report the number written; the
+ * chosen one is report[0]. */
 int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,
                  const int32_t* cells, int32_t n_reps, pxd_tune_entry* report, int32_t max_report,
                  int32_t* n_report);

@@ -61,9 +61,10 @@ struct Tuning {
   bool valid = false;
   double ms = 0;
 };
-constexpr int kSizeClasses = 4;  // Q = 1, 2, 4, 8
+constexpr int kSizeClasses = 5;  // Q = 1, 2, 4, 8, 16 (active sizes up to 256 Q)
 constexpr int kPrecisions = 4;   // PXD_PREC_*
-int size_class(int Q) { return Q <= 1 ? 0 : Q <= 2 ? 1 : Q <= 4 ? 2 : 3; }
+constexpr int kClassQ[kSizeClasses] = {1, 2, 4, 8, 16};
+int size_class(int Q) { return Q <= 1 ? 0 : Q <= 2 ? 1 : Q <= 4 ? 2 : Q <= 8 ? 3 : 4; }
 
 }  // namespace
 
@@ -93,6 +94,11 @@ struct pxd_ctx {
   bool stats_pending_counts = false;
   bool stats_lowrank = false;  // the last call was a low-rank one (stage events differ)
   const int* stats_counts = nullptr;  // device counters of the last dense call ([1] fallbacks, [2] refinement steps)
+  // tiled path, when profiling is on: one event pair per trailing-update launch
+  bool profile = false;
+  std::vector<hipEvent_t> upd_ev;
+  int n_upd = 0;
+  double upd_flops = 0;
   // tiled path: item order of the call (host copy) and its device copy
   std::vector<int> h_items, h_fb;
   DevBuf tl_items;
@@ -136,6 +142,7 @@ Tuning resolve(const pxd_ctx* ctx, int Q) {
   if (ctx->forced) return *ctx->forced;
   const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(Q)];
   Tuning r = t.valid ? t : Tuning{};
+  if (r.wg_per_cu < 1) r.wg_per_cu = 2;  // a tuned tiled record says nothing about the persistent grid
   if (ctx->opt.wg_per_cu > 0) r.wg_per_cu = std::min(ctx->opt.wg_per_cu, 2);
   if (ctx->opt.half_subpanel == 1 || ctx->opt.half_subpanel == 2) r.half_sb = ctx->opt.half_subpanel - 1;
   if (ctx->opt.schedule != PXD_SCHED_AUTO) r.schedule = ctx->opt.schedule;
@@ -146,8 +153,9 @@ Tuning resolve(const pxd_ctx* ctx, int Q) {
 // tuned choice for the size class, else tiled only above the persistent
 // kernels' 2,048 limit.
 bool use_tiled(const pxd_ctx* ctx, int nmax) {
+  const bool no_c64 = ctx->opt.precision != PXD_PREC_FP64 && !ctx->Z64.p;
+  if (ctx->opt.lu_path == PXD_PATH_TILED || nmax > 2048 || no_c64) return true;
   if (ctx->opt.lu_path == PXD_PATH_PERSISTENT) return false;
-  if (ctx->opt.lu_path == PXD_PATH_TILED || nmax > 2048) return true;
   if (ctx->forced) return ctx->forced->tiled;
   const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(pxd::rows_per_thread(nmax))];
   return t.valid && t.tiled;
@@ -224,7 +232,27 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
     for (int K = 0; K < ne_max; K += kb) {
       HIPCHK(ctx, pxd::tl_panel(s, tp, K, nmax));
       HIPCHK(ctx, pxd::tl_trsm(s, tp, K, nmax));
-      HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax));
+      if (ctx->profile) {  // events around the launch; algorithmic work 8 kbb (N - Kend)(ncols - Kend) per item
+        if ((int)ctx->upd_ev.size() < 2 * (ctx->n_upd + 1)) {
+          for (int e = 0; e < 2; ++e) {
+            hipEvent_t ev;
+            HIPCHK(ctx, hipEventCreate(&ev));
+            ctx->upd_ev.push_back(ev);
+          }
+        }
+        for (int i = i0; i < i0 + B; ++i) {
+          const int N = ctx->hNc[list[i] / F], Ne = mixed ? N : N - P, nc = mixed ? N : N + P;
+          if (K >= Ne) continue;
+          const int kend = K + std::min(kb, Ne - K);
+          ctx->upd_flops += 8.0 * (kend - K) * (double)(N - kend) * (double)(nc - kend);
+        }
+        HIPCHK(ctx, hipEventRecord(ctx->upd_ev[2 * ctx->n_upd], s));
+        HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax));
+        HIPCHK(ctx, hipEventRecord(ctx->upd_ev[2 * ctx->n_upd + 1], s));
+        ++ctx->n_upd;
+      } else {
+        HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax));
+      }
     }
     HIPCHK(ctx, pxd::tl_finish(s, tp, nmax));
   }
@@ -301,6 +329,7 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   const bool events = !capturing;
   const int M = ctx->M, F = ctx->F, P = ctx->P;
   if (events) ctx->stats = pxd_stats{}, ctx->stats_lowrank = false;
+  ctx->n_upd = 0, ctx->upd_flops = 0;
   if (C == 0) return PXD_OK;
   const long long items = (long long)C * F;
   int *Nc, *Ilist, *order, *cnt, *item_status, *fb_list = nullptr;
@@ -405,6 +434,19 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
     ctx->stats_counts = cnt;
   }
   return PXD_OK;
+}
+
+// The complex64 copy of the parent the mixed modes gather their factor from,
+// made only when it fits beside the complex128 parent with 8 GiB to spare;
+// without it the tiled path gathers and rounds the complex128 parent.
+hipError_t make_c64_copy(pxd_ctx* ctx, size_t n) {
+  if (ctx->opt.precision == PXD_PREC_FP64) return hipSuccess;
+  size_t fr = 0, tot = 0;
+  hipError_t e = hipMemGetInfo(&fr, &tot);
+  if (e != hipSuccess) return e;
+  if (fr < n * 8 + (size_t(8) << 30)) return hipSuccess;
+  if ((e = ctx->Z64.ensure(n * 8)) != hipSuccess) return e;
+  return pxd::launch_to_c64(ctx->stream, ctx->Z128.as<double2>(), ctx->Z64.as<float2>(), n);
 }
 
 int check_flips(pxd_ctx* ctx, int n_cand, const int32_t* offsets, const int32_t* cells) {
@@ -673,6 +715,7 @@ void pxd_destroy(pxd_ctx* ctx) {
   ctx->eb.release();
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
+  for (auto& ev : ctx->upd_ev) (void)hipEventDestroy(ev);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -687,10 +730,7 @@ int pxd_load_parent(pxd_ctx* ctx, int32_t M, int32_t F, const double* freqs_hz, 
   ctx->Z64.release();
   HIPCHK(ctx, ctx->Z128.ensure(n * 16));
   HIPCHK(ctx, hipMemcpyAsync(ctx->Z128.p, Z, n * 16, hipMemcpyHostToDevice, ctx->stream));
-  if (ctx->opt.precision != PXD_PREC_FP64) {
-    HIPCHK(ctx, ctx->Z64.ensure(n * 8));
-    HIPCHK(ctx, pxd::launch_to_c64(ctx->stream, ctx->Z128.as<double2>(), ctx->Z64.as<float2>(), n));
-  }
+  HIPCHK(ctx, make_c64_copy(ctx, n));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->M = M;
   ctx->F = F;
@@ -722,10 +762,7 @@ int pxd_load_parent_problem(pxd_ctx* ctx, const pxd_problem* p, int32_t F, const
     ctx->Z128.release();
     return ctx->fail(rc, err);
   }
-  if (ctx->opt.precision != PXD_PREC_FP64) {
-    HIPCHK(ctx, ctx->Z64.ensure(n * 8));
-    HIPCHK(ctx, pxd::launch_to_c64(ctx->stream, ctx->Z128.as<double2>(), ctx->Z64.as<float2>(), n));
-  }
+  HIPCHK(ctx, make_c64_copy(ctx, n));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->M = M;
   ctx->F = F;
@@ -916,30 +953,60 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
   const bool sched_fixed = ctx->opt.schedule != PXD_SCHED_AUTO;
   const int sched_lo = sched_fixed ? ctx->opt.schedule : PXD_SCHED_FREQ_MAJOR;
   const int sched_hi = sched_fixed ? ctx->opt.schedule : PXD_SCHED_SIZE_MAJOR;
-  for (int wg = wg_hi; wg >= wg_lo; --wg)
-    for (int half = half_lo; half <= half_hi; ++half)
+  const bool kb_fixed = ctx->opt.tile_kb == 64 || ctx->opt.tile_kb == 128;
+  // the batch's largest active size decides which paths can take it
+  int nmax_batch = 0;
+  {
+    std::vector<int32_t> Nb(n_cand);
+    std::vector<int32_t> idx((size_t)n_cand * ctx->M);
+    rc = pxd_expand(ctx, base_map, n_cand, offsets, cells, Nb.data(), idx.data());
+    if (rc) return rc;
+    nmax_batch = *std::max_element(Nb.begin(), Nb.end());
+  }
+  const bool no_c64 = ctx->opt.precision != PXD_PREC_FP64 && !ctx->Z64.p;
+  const bool try_persistent = ctx->opt.lu_path != PXD_PATH_TILED && nmax_batch <= 2048 && !no_c64;
+  const bool try_tiled = ctx->opt.lu_path != PXD_PATH_PERSISTENT;
+  std::vector<Tuning> cands;
+  if (try_persistent)
+    for (int wg = wg_hi; wg >= wg_lo; --wg)
+      for (int half = half_lo; half <= half_hi; ++half)
+        for (int sched = sched_lo; sched <= sched_hi; ++sched) {
+          Tuning t;
+          t.wg_per_cu = wg, t.half_sb = half, t.schedule = sched, t.tiled = false, t.valid = true;
+          cands.push_back(t);
+        }
+  if (try_tiled)
+    for (int kb : {64, 128}) {
+      if (kb_fixed && kb != ctx->opt.tile_kb) continue;
       for (int sched = sched_lo; sched <= sched_hi; ++sched) {
         Tuning t;
-        t.wg_per_cu = wg, t.half_sb = half, t.schedule = sched, t.valid = true;
-        double best = 1e300;
-        for (int r = 0; r < n_reps; ++r) {
-          ctx->forced = &t;
-          rc = upload_and_evaluate(ctx, base_map, 0, n_cand, offsets, cells);
-          ctx->forced = nullptr;
-          if (rc) return rc;
-          HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-          pxd_stats st{};
-          pxd_get_stats(ctx, &st);
-          best = std::min(best, st.ms_solve + st.ms_fallback);
-          Q = pxd::rows_per_thread(st.max_active);
-        }
-        tried.push_back(pxd_tune_entry{Q, wg, half, sched, best});
+        t.wg_per_cu = 0, t.schedule = sched, t.tiled = true, t.tile_kb = kb, t.valid = true;
+        cands.push_back(t);
       }
+    }
+  for (const Tuning& t : cands) {
+    double best = 1e300;
+    for (int r = 0; r < n_reps; ++r) {
+      ctx->forced = &t;
+      rc = upload_and_evaluate(ctx, base_map, 0, n_cand, offsets, cells);
+      ctx->forced = nullptr;
+      if (rc) return rc;
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      pxd_stats st{};
+      pxd_get_stats(ctx, &st);
+      best = std::min(best, st.ms_solve + st.ms_fallback);
+      Q = pxd::rows_per_thread(st.max_active);
+    }
+    tried.push_back(pxd_tune_entry{Q, t.wg_per_cu, t.half_sb, t.schedule, t.tiled ? PXD_PATH_TILED
+                                                                                   : PXD_PATH_PERSISTENT,
+                                   t.tile_kb, best});
+  }
   std::stable_sort(tried.begin(), tried.end(),
                    [](const pxd_tune_entry& a, const pxd_tune_entry& b) { return a.ms < b.ms; });
   const pxd_tune_entry& w = tried.front();
   Tuning& slot = ctx->tuned[ctx->opt.precision][size_class(Q)];
   slot.wg_per_cu = w.wg_per_cu, slot.half_sb = w.half_subpanel, slot.schedule = w.schedule;
+  slot.tiled = w.lu_path == PXD_PATH_TILED, slot.tile_kb = w.tile_kb;
   slot.ms = w.ms, slot.valid = true;
   const int n = std::min<int>(max_report, (int)tried.size());
   for (int i = 0; i < n; ++i) report[i] = tried[i];
@@ -951,12 +1018,13 @@ int pxd_tune_save(const pxd_ctx* ctx, const char* path) {
   if (!ctx || !path) return pxd::set_thread_error(PXD_EINVAL, "null argument");
   FILE* f = std::fopen(path, "w");
   if (!f) return pxd::set_thread_error(PXD_EINVAL, std::string("cannot write ") + path);
-  std::fprintf(f, "# precision rows_per_thread wg_per_cu half_subpanel schedule ms\n");
-  const int Qs[kSizeClasses] = {1, 2, 4, 8};
+  std::fprintf(f, "# precision rows_per_thread wg_per_cu half_subpanel schedule ms lu_path tile_kb\n");
   for (int prec = 0; prec < kPrecisions; ++prec)
     for (int q = 0; q < kSizeClasses; ++q) {
       const Tuning& t = ctx->tuned[prec][q];
-      if (t.valid) std::fprintf(f, "%d %d %d %d %d %.6f\n", prec, Qs[q], t.wg_per_cu, t.half_sb, t.schedule, t.ms);
+      if (t.valid)
+        std::fprintf(f, "%d %d %d %d %d %.6f %d %d\n", prec, kClassQ[q], t.wg_per_cu, t.half_sb, t.schedule, t.ms,
+                     t.tiled ? PXD_PATH_TILED : PXD_PATH_PERSISTENT, t.tile_kb);
     }
   std::fclose(f);
   return PXD_OK;
@@ -970,17 +1038,20 @@ int pxd_tune_load(pxd_ctx* ctx, const char* path) {
   int rc = PXD_OK;
   while (std::fgets(line, sizeof line, f)) {
     if (line[0] == '#' || line[0] == '\n') continue;
-    int prec, Q, wg, half, sched;
+    int prec, Q, wg, half, sched, path = PXD_PATH_PERSISTENT, kb = 0;
     double ms;
-    if (std::sscanf(line, "%d %d %d %d %d %lf", &prec, &Q, &wg, &half, &sched, &ms) != 6 || prec < 0 ||
-        prec >= kPrecisions ||
-        (Q != 1 && Q != 2 && Q != 4 && Q != 8) || wg < 1 || wg > 2 || half < 0 || half > 1 ||
-        sched < PXD_SCHED_FREQ_MAJOR || sched > PXD_SCHED_SIZE_MAJOR) {
+    const int got = std::sscanf(line, "%d %d %d %d %d %lf %d %d", &prec, &Q, &wg, &half, &sched, &ms, &path, &kb);
+    if ((got != 6 && got != 8) || prec < 0 || prec >= kPrecisions ||
+        (Q != 1 && Q != 2 && Q != 4 && Q != 8 && Q != 16) || wg < 0 || wg > 2 || half < 0 || half > 1 ||
+        sched < PXD_SCHED_FREQ_MAJOR || sched > PXD_SCHED_SIZE_MAJOR ||
+        (path != PXD_PATH_PERSISTENT && path != PXD_PATH_TILED) || (kb != 0 && kb != 64 && kb != 128) ||
+        (path == PXD_PATH_PERSISTENT && wg < 1)) {
       rc = ctx->fail(PXD_EINVAL, std::string("malformed tuning line: ") + line);
       break;
     }
     Tuning& t = ctx->tuned[prec][size_class(Q)];
     t.wg_per_cu = wg, t.half_sb = half, t.schedule = sched, t.ms = ms, t.valid = true;
+    t.tiled = path == PXD_PATH_TILED, t.tile_kb = kb;
   }
   std::fclose(f);
   return rc;
@@ -1116,6 +1187,12 @@ int pxd_gather(pxd_ctx* ctx, int32_t f, int32_t N, const int32_t* idx, double* Z
   return rc;
 }
 
+int pxd_set_profiling(pxd_ctx* ctx, int32_t on) {
+  if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  ctx->profile = on != 0;
+  return PXD_OK;
+}
+
 int pxd_refine_verdict(int32_t iters, int32_t ir_max, double m, double m_prev, double target) {
   if (iters < 1 || ir_max < 1) return pxd::set_thread_error(PXD_EINVAL, "iters and ir_max must be >= 1");
   return pxd::refine_verdict(iters, ir_max, m, m_prev, target);
@@ -1137,6 +1214,12 @@ int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out) {
       out->ms_solve = b;
     }
     if (hipEventElapsedTime(&c, ctx->ev[3], ctx->ev[4]) == hipSuccess) out->ms_fom = c;
+    out->update_launches = ctx->n_upd;
+    out->update_gflop = ctx->upd_flops / 1e9;
+    for (int i = 0; i < ctx->n_upd; ++i) {
+      float u = 0;
+      if (hipEventElapsedTime(&u, ctx->upd_ev[2 * i], ctx->upd_ev[2 * i + 1]) == hipSuccess) out->ms_update += u;
+    }
     float d = 0;
     if (ctx->stats_pending_counts && hipEventElapsedTime(&d, ctx->ev[2], ctx->ev[3]) == hipSuccess) {
       out->ms_fallback = d;

@@ -58,13 +58,14 @@ class Stats(C.Structure):
         ("items", C.c_int64), ("fallbacks", C.c_int64), ("ir_iterations", C.c_int64),
         ("max_active", C.c_int32), ("min_active", C.c_int32),
         ("ms_expand", C.c_double), ("ms_solve", C.c_double), ("ms_fallback", C.c_double), ("ms_fom", C.c_double),
-        ("ms_base_inverse", C.c_double), ("base_reused", C.c_int32), ("reserved", C.c_int32),
+        ("ms_base_inverse", C.c_double), ("base_reused", C.c_int32), ("update_launches", C.c_int32),
+        ("ms_update", C.c_double), ("update_gflop", C.c_double),
     ]
 
 
 class TuneEntry(C.Structure):
     _fields_ = [("rows_per_thread", C.c_int32), ("wg_per_cu", C.c_int32), ("half_subpanel", C.c_int32),
-                ("schedule", C.c_int32), ("ms", C.c_double)]
+                ("schedule", C.c_int32), ("lu_path", C.c_int32), ("tile_kb", C.c_int32), ("ms", C.c_double)]
 
 
 _VP = C.c_void_p
@@ -90,6 +91,7 @@ _SIGS = {
     "pxd_expand": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "pxd_gather": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP]),
     "pxd_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
+    "pxd_set_profiling": (C.c_int, [_VP, C.c_int32]),
     "pxd_refine_verdict": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double]),
     "pxd_evaluate_maps": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "pxd_evaluate_maps_device": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
@@ -366,6 +368,11 @@ class Evaluator:
         out = np.empty((len(idx), len(idx)), np.complex128)
         self._c(lib().pxd_gather(self._h, f, len(idx), _ptr(idx), _ptr(out)))
         return out
+
+    def set_profiling(self, on=True):
+        """Time every trailing-update launch of the tiled path (stats()['ms_update'])
+        and count its algorithmic work (stats()['update_gflop'])."""
+        self._c(lib().pxd_set_profiling(self._h, 1 if on else 0))
 
     def stats(self):
         s = Stats()

@@ -78,16 +78,22 @@ def test_autotune_picks_a_measured_configuration(tmp_path):
     off, cells = spec.flips()
     ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_MIXED32)
     rep = ev.autotune(base, off, cells, n_reps=2)
-    assert len(rep) == 8
+    # persistent path: workgroups per CU x sub-panel width x item order;
+    # tiled path: block-column width x item order
+    assert len(rep) == 12
     assert [r["ms"] for r in rep] == sorted(r["ms"] for r in rep)
     assert all(r["ms"] > 0 for r in rep)
-    assert {(r["wg_per_cu"], r["half_subpanel"], r["schedule"]) for r in rep} == set(
+    pers = [r for r in rep if r["lu_path"] == pxd.PATH_PERSISTENT]
+    tiled = [r for r in rep if r["lu_path"] == pxd.PATH_TILED]
+    assert {(r["wg_per_cu"], r["half_subpanel"], r["schedule"]) for r in pers} == set(
         itertools.product((1, 2), (0, 1), (1, 2)))
+    assert {(r["tile_kb"], r["schedule"]) for r in tiled} == set(itertools.product((64, 128), (1, 2)))
     path = str(tmp_path / "tune.txt")
     ev.tune_save(path)
     lines = [l.split() for l in open(path) if not l.startswith("#")]
     assert len(lines) == 1 and lines[0][0] == "1"
     assert [int(x) for x in lines[0][2:5]] == [rep[0]["wg_per_cu"], rep[0]["half_subpanel"], rep[0]["schedule"]]
+    assert [int(x) for x in lines[0][6:8]] == [rep[0]["lu_path"], rep[0]["tile_kb"]]
     # the tuned configuration is used and still matches the oracle
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
@@ -114,10 +120,19 @@ def test_autotune_keeps_fixed_options():
     off, cells = spec.flips()
     ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_FP64, half_subpanel=1, schedule=pxd.SCHED_FREQ_MAJOR)
     rep = ev.autotune(base, off, cells)
-    assert sorted(r["wg_per_cu"] for r in rep) == [1, 2]
+    pers = [r for r in rep if r["lu_path"] == pxd.PATH_PERSISTENT]
+    assert sorted(r["wg_per_cu"] for r in pers) == [1, 2]
+    assert sorted(r["tile_kb"] for r in rep if r["lu_path"] == pxd.PATH_TILED) == [64, 128]
     assert all(r["half_subpanel"] == 0 and r["schedule"] == pxd.SCHED_FREQ_MAJOR for r in rep)
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
+    check(S, F, S_o, F_o, pxd.PREC_FP64)
+    ev.close()
+    # a fixed path and block width leave only the other choices
+    ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_FP64, lu_path=pxd.PATH_TILED, tile_kb=128)
+    rep = ev.autotune(base, off, cells)
+    assert {(r["lu_path"], r["tile_kb"]) for r in rep} == {(pxd.PATH_TILED, 128)} and len(rep) == 2
+    S, F, status, am = ev.evaluate_flips(base, off, cells)
     check(S, F, S_o, F_o, pxd.PREC_FP64)
     ev.close()
 
