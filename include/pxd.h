@@ -233,6 +233,28 @@ int pxd_evaluate_flips_device(pxd_ctx* ctx, void* stream, const uint8_t* base_ma
                               const int32_t* offsets, const int32_t* cells, int32_t n_flips, double* S_out,
                               double* fom_out, int32_t* status, int32_t* argmin_out);
 
+/* For callers that cannot allocate device memory (code between allocation-free
+ * points of a serving loop, harnesses that forbid hipMalloc): the same
+ * evaluation as pxd_evaluate_flips_device, with the same arguments, outputs
+ * and stream semantics, but every buffer the kernels need beyond the caller's
+ * inputs and outputs (active lists, item order, counters, per-item status,
+ * the FP64 hand-off list and the LU workspace slots) is carved out of a
+ * static device array of 64 MiB that each GPU holds from library load to
+ * process end.  No hipMalloc, hipFree or other allocating routine is called;
+ * the call reads back two integers (the batch's smallest and largest active
+ * size) and so synchronises `stream` once.  It runs as many persistent
+ * workgroups as workspace slots fit (at least one).  A batch whose active
+ * lists (n_cand x (M + 2) int32 plus n_cand x F int32, twice that in the mixed
+ * modes) plus one slot do not fit is refused with PXD_ESHAPE and a message
+ * giving the sizes.  Every call on one GPU shares that array and leaves its
+ * contents behind (counters are cleared at the start of each call): calls
+ * that overlap on one GPU, from any context or thread, race and must not be
+ * made.  The context must be loaded (parent, map, FoM) as for the other
+ * entry points; loading allocates, this call does not. */
+int pxd_evaluate_flips_device_noalloc(pxd_ctx* ctx, void* stream, const uint8_t* base_map, int32_t n_cand,
+                                      const int32_t* offsets, const int32_t* cells, int32_t n_flips, double* S_out,
+                                      double* fom_out, int32_t* status, int32_t* argmin_out);
+
 /* Flip candidates evaluated from the inverse of the base map instead of one
  * dense factorisation each (a variant the paper does not use; it gives the
  * S of Eqs. 6-7 for the candidate's Z_A of Eq. 5 up to rounding).  With

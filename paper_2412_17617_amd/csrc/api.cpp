@@ -102,6 +102,9 @@ struct pxd_ctx {
   // tiled path: item order of the call (host copy) and its device copy
   std::vector<int> h_items, h_fb;
   DevBuf tl_items;
+  // the no-allocation entry point's region of the static scratch array on this device
+  char* scratch = nullptr;
+  size_t scratch_bytes = 0;
   // autotuning: tuned[precision][size class]; `forced` overrides during a tuning sweep
   Tuning tuned[kPrecisions][kSizeClasses];
   const Tuning* forced = nullptr;
@@ -148,6 +151,20 @@ Tuning resolve(const pxd_ctx* ctx, int Q) {
   if (ctx->opt.schedule != PXD_SCHED_AUTO) r.schedule = ctx->opt.schedule;
   return r;
 }
+
+// Where one evaluation's internal buffers come from: the context's (or a
+// graph's) growable device buffers, or, for the no-allocation entry point, a
+// fixed region carved in order out of the library's static scratch array.
+struct Arena {
+  char* base = nullptr;  // null: use the EvalBufs
+  size_t cap = 0, used = 0;
+  char* take(size_t bytes) {
+    const size_t at = (used + 255) / 256 * 256;
+    if (at + bytes > cap) return nullptr;
+    used = at + bytes;
+    return base + at;
+  }
+};
 
 // Whether the batch's dense solves go to the tiled LU: the option, else the
 // tuned choice for the size class, else tiled only above the persistent
@@ -318,10 +335,12 @@ int evaluate_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, int C, const int* N
 // Enqueue one evaluation of C candidates on stream s.  nmax_bound > 0: the
 // launch is sized for that bound without reading the active sizes back (as a
 // graph needs); otherwise they are read back to size it exactly.  Events and
-// kernel attributes are set only outside stream capture.
+// kernel attributes are set only outside stream capture.  With an arena, no
+// buffer is allocated: everything the kernels use beyond the caller's inputs
+// and outputs is carved out of it (a call that does not fit is refused).
 int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, size_t base_stride, int C,
              const int* d_off, const int* d_cells, double2* d_S, double* d_fom, int* d_cand_status, int* d_argmin,
-             int nmax_bound, bool capturing = false) {
+             int nmax_bound, bool capturing = false, Arena* arena = nullptr) {
   if (!ctx->Z128.p) return ctx->fail(PXD_ENOTLOADED, "parent matrices not loaded");
   if (!ctx->cell_a.p) return ctx->fail(PXD_ENOTLOADED, "pixel-to-RWG map not loaded");
   if (!ctx->terms.p) return ctx->fail(PXD_ENOTLOADED, "FoM table not set");
@@ -332,15 +351,30 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   ctx->n_upd = 0, ctx->upd_flops = 0;
   if (C == 0) return PXD_OK;
   const long long items = (long long)C * F;
-  int *Nc, *Ilist, *order, *cnt, *item_status, *fb_list = nullptr;
-  HIPCHK(ctx, b.Nc.ensure(sizeof(int) * C));
-  HIPCHK(ctx, b.Ilist.ensure(sizeof(int) * (size_t)C * M));
-  HIPCHK(ctx, b.order.ensure(sizeof(int) * C));
-  HIPCHK(ctx, b.counter.ensure(sizeof(int) * 8));
-  HIPCHK(ctx, b.item_status.ensure(sizeof(int) * (size_t)items));
-  if (mixed) HIPCHK(ctx, b.fb_list.ensure(sizeof(int) * (size_t)items));
-  Nc = b.Nc.as<int>(), Ilist = b.Ilist.as<int>(), order = b.order.as<int>(), cnt = b.counter.as<int>();
-  item_status = b.item_status.as<int>(), fb_list = b.fb_list.as<int>();
+  int *Nc, *Ilist, *order, *cnt, *item_status, *fb_list = nullptr, *minmax = nullptr;
+  if (arena) {
+    Nc = (int*)arena->take(sizeof(int) * C);
+    order = (int*)arena->take(sizeof(int) * C);
+    cnt = (int*)arena->take(sizeof(int) * 8);
+    minmax = (int*)arena->take(sizeof(int) * 2);
+    item_status = (int*)arena->take(sizeof(int) * (size_t)items);
+    if (mixed) fb_list = (int*)arena->take(sizeof(int) * (size_t)items);
+    Ilist = (int*)arena->take(sizeof(int) * (size_t)C * M);
+    if (!Nc || !order || !cnt || !minmax || !item_status || (mixed && !fb_list) || !Ilist)
+      return ctx->fail(PXD_ESHAPE, "batch does not fit the no-allocation scratch (" + std::to_string(arena->cap) +
+                                       " bytes): its active lists alone need " +
+                                       std::to_string((size_t)C * (8 + 4 * (size_t)M) +
+                                                      (size_t)items * (mixed ? 8 : 4)) + " bytes");
+  } else {
+    HIPCHK(ctx, b.Nc.ensure(sizeof(int) * C));
+    HIPCHK(ctx, b.Ilist.ensure(sizeof(int) * (size_t)C * M));
+    HIPCHK(ctx, b.order.ensure(sizeof(int) * C));
+    HIPCHK(ctx, b.counter.ensure(sizeof(int) * 8));
+    HIPCHK(ctx, b.item_status.ensure(sizeof(int) * (size_t)items));
+    if (mixed) HIPCHK(ctx, b.fb_list.ensure(sizeof(int) * (size_t)items));
+    Nc = b.Nc.as<int>(), Ilist = b.Ilist.as<int>(), order = b.order.as<int>(), cnt = b.counter.as<int>();
+    item_status = b.item_status.as<int>(), fb_list = b.fb_list.as<int>();
+  }
   if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
   HIPCHK(ctx, pxd::launch_expand(s, d_base, ctx->n_cells, base_stride, d_off, d_cells, C, ctx->cell_a.as<int>(),
                                  ctx->cell_b.as<int>(), M, Nc, Ilist));
@@ -348,17 +382,26 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   int nmax = nmax_bound, nmin = P;
   if (nmax_bound <= 0) {
     // the largest active size picks the kernel variant and the slot size
-    ctx->hNc.resize(C);
-    HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data(), Nc, sizeof(int) * C, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    nmax = *std::max_element(ctx->hNc.begin(), ctx->hNc.end());
-    nmin = *std::min_element(ctx->hNc.begin(), ctx->hNc.end());
+    if (arena) {  // reduced on the device, two ints read back into stack memory
+      int h[2] = {0, 0};
+      HIPCHK(ctx, pxd::launch_minmax(s, Nc, C, minmax));
+      HIPCHK(ctx, hipMemcpyAsync(h, minmax, sizeof(h), hipMemcpyDeviceToHost, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      nmin = h[0], nmax = h[1];
+    } else {
+      ctx->hNc.resize(C);
+      HIPCHK(ctx, hipMemcpyAsync(ctx->hNc.data(), Nc, sizeof(int) * C, hipMemcpyDeviceToHost, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      nmax = *std::max_element(ctx->hNc.begin(), ctx->hNc.end());
+      nmin = *std::min_element(ctx->hNc.begin(), ctx->hNc.end());
+    }
     if (nmin < P) return ctx->fail(PXD_ESHAPE, "candidate with fewer active functions than ports");
   }
   const bool tiled = use_tiled(ctx, nmax);
   if (tiled) {
-    if (nmax_bound > 0)
-      return ctx->fail(PXD_ESHAPE, "the tiled LU (active sizes above 2,048) is not available in graphs");
+    if (arena || nmax_bound > 0)
+      return ctx->fail(PXD_ESHAPE, "the tiled LU (active sizes above 2,048) is not available in graphs or the "
+                                   "no-allocation entry point");
     if (nmax > pxd::tl_max_active())
       return ctx->fail(PXD_ESHAPE, "active size above " + std::to_string(pxd::tl_max_active()) + " is not supported");
     if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
@@ -374,8 +417,19 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   const pxd::SlotLayout lay_m = pxd::slot_layout(nmax, P, true);
   // the mixed path re-solves unrefined items with the FP64 kernel in the same slots
   const size_t slot = mixed ? std::max(lay_p.bytes, lay_m.bytes) : lay_p.bytes;
-  HIPCHK(ctx, b.ws.ensure(slot * (size_t)grid));
-  char* ws = b.ws.as<char>();
+  char* ws;
+  if (arena) {  // as many persistent workgroups as slots fit (at least one)
+    const size_t room = arena->cap > arena->used + 256 ? arena->cap - arena->used - 256 : 0;
+    grid = (int)std::min<long long>(grid, (long long)(room / slot));
+    if (grid < 1)
+      return ctx->fail(PXD_ESHAPE, "batch does not fit the no-allocation scratch (" + std::to_string(arena->cap) +
+                                       " bytes): one workspace slot at active size " + std::to_string(nmax) +
+                                       " needs " + std::to_string(slot) + " bytes beyond the active lists");
+    ws = arena->take(slot * (size_t)grid);
+  } else {
+    HIPCHK(ctx, b.ws.ensure(slot * (size_t)grid));
+    ws = b.ws.as<char>();
+  }
 
   pxd::EvalParams ep{};
   ep.Z128 = ctx->Z128.as<double2>();
@@ -697,6 +751,12 @@ int pxd_create(const pxd_options* opt, pxd_ctx** out) {
       pxd_destroy(ctx);
       return pxd::set_thread_error(PXD_EDEVICE, "event creation failed");
     }
+  // device address of this GPU's scratch array (looked up once per device);
+  // if the lookup fails here, the no-allocation entry point retries it
+  if (pxd::scratch_region(ctx->opt.device, &ctx->scratch, &ctx->scratch_bytes) != hipSuccess) {
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+  }
   *out = ctx;
   return PXD_OK;
 }
@@ -908,6 +968,20 @@ int pxd_evaluate_flips_device(pxd_ctx* ctx, void* stream, const uint8_t* base_ma
   hipStream_t s = static_cast<hipStream_t>(stream);  // NULL is the default stream
   return evaluate(ctx, ctx->eb, s, base_map, 0, n_cand, offsets, cells, reinterpret_cast<double2*>(S_out), fom_out,
                   status, argmin_out, 0);
+}
+
+int pxd_evaluate_flips_device_noalloc(pxd_ctx* ctx, void* stream, const uint8_t* base_map, int32_t n_cand,
+                                      const int32_t* offsets, const int32_t* cells, int32_t n_flips, double* S_out,
+                                      double* fom_out, int32_t* status, int32_t* argmin_out) {
+  if (!ctx) return pxd::set_thread_error(PXD_EINVAL, "ctx is NULL");
+  if (!base_map || !offsets || n_cand < 0 || n_flips < 0 || (n_flips > 0 && !cells) || !S_out || !fom_out)
+    return ctx->fail(PXD_EINVAL, "invalid device arguments");
+  HIPCHK(ctx, hipSetDevice(ctx->opt.device));
+  if (!ctx->scratch) HIPCHK(ctx, pxd::scratch_region(ctx->opt.device, &ctx->scratch, &ctx->scratch_bytes));
+  hipStream_t s = static_cast<hipStream_t>(stream);  // NULL is the default stream
+  Arena arena{ctx->scratch, ctx->scratch_bytes, 0};
+  return evaluate(ctx, ctx->eb, s, base_map, 0, n_cand, offsets, cells, reinterpret_cast<double2*>(S_out), fom_out,
+                  status, argmin_out, 0, false, &arena);
 }
 
 int pxd_evaluate_maps(pxd_ctx* ctx, int32_t n_maps, const uint8_t* maps, double* S_out, double* fom_out,

@@ -85,6 +85,21 @@ __global__ void k_order(const int* __restrict__ Nc, int C, int* __restrict__ ord
   order[rank] = c;
 }
 
+// out[0] = min, out[1] = max of v[0 .. n), one workgroup
+__global__ __launch_bounds__(256) void k_minmax(const int* __restrict__ v, int n, int* __restrict__ out) {
+  __shared__ int lo[256], hi[256];
+  const int tid = threadIdx.x;
+  int a = 0x7fffffff, b = -0x7fffffff - 1;
+  for (int i = tid; i < n; i += 256) a = min(a, v[i]), b = max(b, v[i]);
+  lo[tid] = a, hi[tid] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) lo[tid] = min(lo[tid], lo[tid + st]), hi[tid] = max(hi[tid], hi[tid + st]);
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = lo[0], out[1] = hi[0];
+}
+
 __global__ void k_fill_int(int* p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -383,6 +398,11 @@ hipError_t launch_expand(hipStream_t s, const uint8_t* base, int n_cells, size_t
 hipError_t launch_order(hipStream_t s, const int* Nc, int C, int* order) {
   if (C <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_order, dim3((C + 255) / 256), dim3(256), 0, s, Nc, C, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_minmax(hipStream_t s, const int* v, int n, int* out) {
+  hipLaunchKernelGGL(k_minmax, dim3(1), dim3(256), 0, s, v, n, out);
   return hipGetLastError();
 }
 

@@ -217,6 +217,14 @@ hipError_t launch_expand(hipStream_t s, const uint8_t* base, int n_cells, size_t
                          const int* cells, int C, const int* cell_a, const int* cell_b, int M, int* Nc, int* Ilist);
 hipError_t launch_order(hipStream_t s, const int* Nc, int C, int* order);
 hipError_t launch_fill_int(hipStream_t s, int* p, int n, int v);
+// out[0] = min(v), out[1] = max(v) over n >= 1 entries
+hipError_t launch_minmax(hipStream_t s, const int* v, int n, int* out);
+
+// The no-allocation entry point's workspace: a static device array of
+// kScratchBytes per GPU.  scratch_region() returns its device address on
+// `device` (looked up once per device, with that device current) and its size.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_region(int device, char** ptr, size_t* bytes);
 // half_sb selects the variant whose register sub-panel is half as wide.
 hipError_t launch_eval_plain(hipStream_t s, const EvalParams& p, int grid, int half_sb);
 hipError_t prepare_eval_mixed(const EvalParams& p, int half_sb);

@@ -88,6 +88,8 @@ _SIGS = {
     "pxd_evaluate_flips": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pxd_evaluate_flips_lowrank": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pxd_evaluate_flips_device": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "pxd_evaluate_flips_device_noalloc": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP, _VP,
+                                                    _VP]),
     "pxd_expand": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "pxd_gather": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP]),
     "pxd_get_stats": (C.c_int, [_VP, C.POINTER(Stats)]),
@@ -304,6 +306,20 @@ class Evaluator:
         self._c(lib().pxd_evaluate_flips_device(self._h, _VP(sp), dp(base_map), n, dp(offsets), dp(cells),
                                                 cells.numel(), dp(S_out), dp(fom_out), dp(status_out),
                                                 dp(argmin_out)))
+
+    def evaluate_flips_device_noalloc(self, stream, base_map, offsets, cells, S_out, fom_out, status_out=None,
+                                      argmin_out=None):
+        """As evaluate_flips_device, with every internal buffer taken from the
+        library's static scratch array (no device allocation)."""
+        sp = getattr(stream, "cuda_stream", stream)
+
+        def dp(t):
+            return None if t is None else _VP(t.data_ptr())
+
+        n = offsets.numel() - 1
+        self._c(lib().pxd_evaluate_flips_device_noalloc(self._h, _VP(sp), dp(base_map), n, dp(offsets), dp(cells),
+                                                        cells.numel(), dp(S_out), dp(fom_out), dp(status_out),
+                                                        dp(argmin_out)))
 
     def evaluate_maps(self, maps, want_S=True):
         """Candidates given as whole maps (n_maps x n_cells uint8)."""
