@@ -141,7 +141,9 @@ typedef struct pxd_options {
   int32_t half_subpanel;   /* register sub-panel of the LU: 1 full width, 2 half width (0 = tuned, else full) */
   int32_t schedule;        /* PXD_SCHED_* */
   int32_t lu_path;         /* PXD_PATH_*: which dense LU solves the items */
-  int32_t tile_kb;         /* tiled path: block-column width 64 or 128 (0 = tuned, else 64) */
+  int32_t tile_kb;         /* tiled path: block-column width 64 or 128 (0 = tuned, else 128) */
+  int32_t tile_shape;      /* tiled path: output tile of the trailing update, 1 = 128 x 64 (two workgroups
+                              per CU), 2 = 64 x 64 (three per CU); 0 = tuned, else 2 */
   double ws_gib;           /* tiled path: workspace cap in GiB (0 = 80 % of the free device memory,
                               at most 64 GiB); fixes how many items are factored together */
 } pxd_options;
@@ -321,6 +323,8 @@ typedef struct pxd_tune_entry {
   int32_t wg_per_cu, half_subpanel, schedule; /* persistent path (wg_per_cu, half_subpanel 0 for tiled) */
   int32_t lu_path;         /* PXD_PATH_PERSISTENT or PXD_PATH_TILED */
   int32_t tile_kb;         /* tiled path: block-column width */
+  int32_t tile_shape;      /* tiled path: trailing-update output tile (1 = 128 x 64, 2 = 64 x 64) */
+  int32_t reserved;
   double ms;               /* evaluator time (solve + fallback), best of n_reps */
 } pxd_tune_entry;
 
@@ -329,9 +333,10 @@ typedef struct pxd_tune_entry {
  * batch's precision and size class; later calls whose options say "tuned"
  * use it.  Configurations: the persistent path (active sizes up to 2,048;
  * workgroups per CU 1 or 2 x register sub-panel full or half width x item
- * order) and the tiled path (block columns of 64 or 128 x item order).  A
- * choice the context's options fix (lu_path, tile_kb 64/128, wg_per_cu > 0,
- * half_subpanel 1 or 2, schedule not AUTO) is not searched.  report (may be
+ * order) and the tiled path (block columns of 64 or 128 x output tiles of
+ * 128 x 64 or 64 x 64 x item order).  A choice the context's options fix
+ * (lu_path, tile_kb 64/128, tile_shape 1/2, wg_per_cu > 0, half_subpanel 1
+ * or 2, schedule not AUTO) is not searched.  report (may be
  * NULL) receives up to max_report entries, *n_report the number written; the
  * chosen one is report[0]. */
 int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const int32_t* offsets,

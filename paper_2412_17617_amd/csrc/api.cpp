@@ -57,7 +57,8 @@ struct EvalBufs {
 struct Tuning {
   int wg_per_cu = 2, half_sb = 0, schedule = PXD_SCHED_FREQ_MAJOR;
   bool tiled = false;  // dense LU path (PXD_PATH_TILED when true)
-  int tile_kb = 0;     // tiled path: block-column width (0 = default 64)
+  int tile_kb = 0;     // tiled path: block-column width (0 = default 128)
+  int tile_shape = 0;  // tiled path: update tile, 1 = 128 x 64, 2 = 64 x 64 (0 = default 2)
   bool valid = false;
   double ms = 0;
 };
@@ -94,6 +95,10 @@ struct pxd_ctx {
   bool stats_pending_counts = false;
   bool stats_lowrank = false;  // the last call was a low-rank one (stage events differ)
   const int* stats_counts = nullptr;  // device counters of the last dense call ([1] fallbacks, [2] refinement steps)
+  // tiled path: look-ahead stream for the next block column's panel, and the
+  // two events that order it against the call's stream
+  hipStream_t aux = nullptr;
+  hipEvent_t la_ev[2] = {};
   // tiled path, when profiling is on: one event pair per trailing-update launch
   bool profile = false;
   std::vector<hipEvent_t> upd_ev;
@@ -182,7 +187,14 @@ int tile_kb(const pxd_ctx* ctx, int nmax) {
   if (ctx->opt.tile_kb == 64 || ctx->opt.tile_kb == 128) return ctx->opt.tile_kb;
   if (ctx->forced && ctx->forced->tile_kb) return ctx->forced->tile_kb;
   const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(pxd::rows_per_thread(nmax))];
-  return (t.valid && t.tile_kb) ? t.tile_kb : 64;
+  return (t.valid && t.tile_kb) ? t.tile_kb : 128;
+}
+
+int tile_shape(const pxd_ctx* ctx, int nmax) {
+  if (ctx->opt.tile_shape == 1 || ctx->opt.tile_shape == 2) return ctx->opt.tile_shape;
+  if (ctx->forced && ctx->forced->tile_shape) return ctx->forced->tile_shape;
+  const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(pxd::rows_per_thread(nmax))];
+  return (t.valid && t.tile_shape) ? t.tile_shape : 2;
 }
 
 // Workspace cap of the tiled path in bytes: the option, else 80 % of the
@@ -192,6 +204,37 @@ size_t tiled_ws_cap(const pxd_ctx* ctx, size_t held) {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
   return std::min<size_t>((size_t)(0.8 * (double)(fr + held)), size_t(64) << 30);
+}
+
+// One trailing-update launch of the tiled path (columns [Kend + cb, Kend + ce)
+// of each item), bracketed by events and counted when profiling is on.
+int tiled_update(pxd_ctx* ctx, hipStream_t s, const pxd::TlParams& tp, const std::vector<int>& list, int i0, int B,
+                 int K, int nmax, int cb, int ce, bool mixed) {
+  if (!ctx->profile) {
+    HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax, cb, ce));
+    return PXD_OK;
+  }
+  const int F = ctx->F, P = ctx->P, kb = tp.kb;
+  if ((int)ctx->upd_ev.size() < 2 * (ctx->n_upd + 1)) {
+    for (int e = 0; e < 2; ++e) {
+      hipEvent_t ev;
+      HIPCHK(ctx, hipEventCreate(&ev));
+      ctx->upd_ev.push_back(ev);
+    }
+  }
+  // algorithmic work: 8 kbb (N - Kend) x (the launch's columns) real flops per item
+  for (int i = i0; i < i0 + B; ++i) {
+    const int N = ctx->hNc[list[i] / F], Ne = mixed ? N : N - P, nc = mixed ? N : N + P;
+    if (K >= Ne) continue;
+    const int kend = K + std::min(kb, Ne - K);
+    const long long c_lo = kend + (long long)cb, c_hi = std::min<long long>(nc, kend + (long long)ce);
+    if (c_hi > c_lo) ctx->upd_flops += 8.0 * (kend - K) * (double)(N - kend) * (double)(c_hi - c_lo);
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->upd_ev[2 * ctx->n_upd], s));
+  HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax, cb, ce));
+  HIPCHK(ctx, hipEventRecord(ctx->upd_ev[2 * ctx->n_upd + 1], s));
+  ++ctx->n_upd;
+  return PXD_OK;
 }
 
 // Factor and solve the items `list[0 .. n)` (c * F + f) with the tiled LU in
@@ -225,6 +268,7 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
   tp.ws = b.ws.as<char>();
   tp.mixed = mixed ? 1 : 0;
   tp.kb = kb;
+  tp.shape = tile_shape(ctx, nmax_all) - 1;
   tp.half = ctx->opt.precision == PXD_PREC_MIXED_BF16 ? PXD_HALF_BF16
             : ctx->opt.precision == PXD_PREC_MIXED_F16 ? PXD_HALF_F16 : PXD_HALF_NONE;
   tp.S = d_S;
@@ -246,29 +290,28 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
     tp.slot_bytes = tp.lay.bytes;
     const int ne_max = mixed ? nmax : nmax - P;
     HIPCHK(ctx, pxd::tl_gather(s, tp, nmax));
+    if (ne_max > 0) {
+      HIPCHK(ctx, pxd::tl_panel(s, tp, 0, nmax));
+      HIPCHK(ctx, pxd::tl_trsm(s, tp, 0, nmax));
+    }
+    // Look-ahead: the update of the next block column's columns comes first;
+    // then the next panel runs on the auxiliary stream while the rest of the
+    // update runs here, and the next interchange/U12 step waits for both.
     for (int K = 0; K < ne_max; K += kb) {
-      HIPCHK(ctx, pxd::tl_panel(s, tp, K, nmax));
-      HIPCHK(ctx, pxd::tl_trsm(s, tp, K, nmax));
-      if (ctx->profile) {  // events around the launch; algorithmic work 8 kbb (N - Kend)(ncols - Kend) per item
-        if ((int)ctx->upd_ev.size() < 2 * (ctx->n_upd + 1)) {
-          for (int e = 0; e < 2; ++e) {
-            hipEvent_t ev;
-            HIPCHK(ctx, hipEventCreate(&ev));
-            ctx->upd_ev.push_back(ev);
-          }
-        }
-        for (int i = i0; i < i0 + B; ++i) {
-          const int N = ctx->hNc[list[i] / F], Ne = mixed ? N : N - P, nc = mixed ? N : N + P;
-          if (K >= Ne) continue;
-          const int kend = K + std::min(kb, Ne - K);
-          ctx->upd_flops += 8.0 * (kend - K) * (double)(N - kend) * (double)(nc - kend);
-        }
-        HIPCHK(ctx, hipEventRecord(ctx->upd_ev[2 * ctx->n_upd], s));
-        HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax));
-        HIPCHK(ctx, hipEventRecord(ctx->upd_ev[2 * ctx->n_upd + 1], s));
-        ++ctx->n_upd;
-      } else {
-        HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax));
+      const bool next = K + kb < ne_max;
+      int rc = tiled_update(ctx, s, tp, list, i0, B, K, nmax, 0, kb, mixed);
+      if (rc) return rc;
+      if (next) {
+        HIPCHK(ctx, hipEventRecord(ctx->la_ev[0], s));
+        HIPCHK(ctx, hipStreamWaitEvent(ctx->aux, ctx->la_ev[0], 0));
+        HIPCHK(ctx, pxd::tl_panel(ctx->aux, tp, K + kb, nmax));
+        HIPCHK(ctx, hipEventRecord(ctx->la_ev[1], ctx->aux));
+      }
+      rc = tiled_update(ctx, s, tp, list, i0, B, K, nmax, kb, 1 << 30, mixed);
+      if (rc) return rc;
+      if (next) {
+        HIPCHK(ctx, hipStreamWaitEvent(s, ctx->la_ev[1], 0));
+        HIPCHK(ctx, pxd::tl_trsm(s, tp, K + kb, nmax));
       }
     }
     HIPCHK(ctx, pxd::tl_finish(s, tp, nmax));
@@ -751,6 +794,15 @@ int pxd_create(const pxd_options* opt, pxd_ctx** out) {
       pxd_destroy(ctx);
       return pxd::set_thread_error(PXD_EDEVICE, "event creation failed");
     }
+  for (auto& ev : ctx->la_ev)
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+      pxd_destroy(ctx);
+      return pxd::set_thread_error(PXD_EDEVICE, "event creation failed");
+    }
+  if ((e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking)) != hipSuccess) {  // default priority
+    pxd_destroy(ctx);
+    return pxd::set_thread_error(PXD_EDEVICE, "stream creation failed");
+  }
   // device address of this GPU's scratch array (looked up once per device);
   // if the lookup fails here, the no-allocation entry point retries it
   if (pxd::scratch_region(ctx->opt.device, &ctx->scratch, &ctx->scratch_bytes) != hipSuccess) {
@@ -776,6 +828,12 @@ void pxd_destroy(pxd_ctx* ctx) {
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
   for (auto& ev : ctx->upd_ev) (void)hipEventDestroy(ev);
+  for (auto& ev : ctx->la_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -1028,6 +1086,7 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
   const int sched_lo = sched_fixed ? ctx->opt.schedule : PXD_SCHED_FREQ_MAJOR;
   const int sched_hi = sched_fixed ? ctx->opt.schedule : PXD_SCHED_SIZE_MAJOR;
   const bool kb_fixed = ctx->opt.tile_kb == 64 || ctx->opt.tile_kb == 128;
+  const bool shape_fixed = ctx->opt.tile_shape == 1 || ctx->opt.tile_shape == 2;
   // the batch's largest active size decides which paths can take it
   int nmax_batch = 0;
   {
@@ -1052,10 +1111,13 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
   if (try_tiled)
     for (int kb : {64, 128}) {
       if (kb_fixed && kb != ctx->opt.tile_kb) continue;
-      for (int sched = sched_lo; sched <= sched_hi; ++sched) {
-        Tuning t;
-        t.wg_per_cu = 0, t.schedule = sched, t.tiled = true, t.tile_kb = kb, t.valid = true;
-        cands.push_back(t);
+      for (int shape : {1, 2}) {
+        if (shape_fixed && shape != ctx->opt.tile_shape) continue;
+        for (int sched = sched_lo; sched <= sched_hi; ++sched) {
+          Tuning t;
+          t.wg_per_cu = 0, t.schedule = sched, t.tiled = true, t.tile_kb = kb, t.tile_shape = shape, t.valid = true;
+          cands.push_back(t);
+        }
       }
     }
   for (const Tuning& t : cands) {
@@ -1071,16 +1133,15 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
       best = std::min(best, st.ms_solve + st.ms_fallback);
       Q = pxd::rows_per_thread(st.max_active);
     }
-    tried.push_back(pxd_tune_entry{Q, t.wg_per_cu, t.half_sb, t.schedule, t.tiled ? PXD_PATH_TILED
-                                                                                   : PXD_PATH_PERSISTENT,
-                                   t.tile_kb, best});
+    tried.push_back(pxd_tune_entry{Q, t.wg_per_cu, t.half_sb, t.schedule,
+                                   t.tiled ? PXD_PATH_TILED : PXD_PATH_PERSISTENT, t.tile_kb, t.tile_shape, 0, best});
   }
   std::stable_sort(tried.begin(), tried.end(),
                    [](const pxd_tune_entry& a, const pxd_tune_entry& b) { return a.ms < b.ms; });
   const pxd_tune_entry& w = tried.front();
   Tuning& slot = ctx->tuned[ctx->opt.precision][size_class(Q)];
   slot.wg_per_cu = w.wg_per_cu, slot.half_sb = w.half_subpanel, slot.schedule = w.schedule;
-  slot.tiled = w.lu_path == PXD_PATH_TILED, slot.tile_kb = w.tile_kb;
+  slot.tiled = w.lu_path == PXD_PATH_TILED, slot.tile_kb = w.tile_kb, slot.tile_shape = w.tile_shape;
   slot.ms = w.ms, slot.valid = true;
   const int n = std::min<int>(max_report, (int)tried.size());
   for (int i = 0; i < n; ++i) report[i] = tried[i];
@@ -1092,13 +1153,13 @@ int pxd_tune_save(const pxd_ctx* ctx, const char* path) {
   if (!ctx || !path) return pxd::set_thread_error(PXD_EINVAL, "null argument");
   FILE* f = std::fopen(path, "w");
   if (!f) return pxd::set_thread_error(PXD_EINVAL, std::string("cannot write ") + path);
-  std::fprintf(f, "# precision rows_per_thread wg_per_cu half_subpanel schedule ms lu_path tile_kb\n");
+  std::fprintf(f, "# precision rows_per_thread wg_per_cu half_subpanel schedule ms lu_path tile_kb tile_shape\n");
   for (int prec = 0; prec < kPrecisions; ++prec)
     for (int q = 0; q < kSizeClasses; ++q) {
       const Tuning& t = ctx->tuned[prec][q];
       if (t.valid)
-        std::fprintf(f, "%d %d %d %d %d %.6f %d %d\n", prec, kClassQ[q], t.wg_per_cu, t.half_sb, t.schedule, t.ms,
-                     t.tiled ? PXD_PATH_TILED : PXD_PATH_PERSISTENT, t.tile_kb);
+        std::fprintf(f, "%d %d %d %d %d %.6f %d %d %d\n", prec, kClassQ[q], t.wg_per_cu, t.half_sb, t.schedule,
+                     t.ms, t.tiled ? PXD_PATH_TILED : PXD_PATH_PERSISTENT, t.tile_kb, t.tile_shape);
     }
   std::fclose(f);
   return PXD_OK;
@@ -1112,10 +1173,11 @@ int pxd_tune_load(pxd_ctx* ctx, const char* path) {
   int rc = PXD_OK;
   while (std::fgets(line, sizeof line, f)) {
     if (line[0] == '#' || line[0] == '\n') continue;
-    int prec, Q, wg, half, sched, path = PXD_PATH_PERSISTENT, kb = 0;
+    int prec, Q, wg, half, sched, path = PXD_PATH_PERSISTENT, kb = 0, shape = 0;
     double ms;
-    const int got = std::sscanf(line, "%d %d %d %d %d %lf %d %d", &prec, &Q, &wg, &half, &sched, &ms, &path, &kb);
-    if ((got != 6 && got != 8) || prec < 0 || prec >= kPrecisions ||
+    const int got =
+        std::sscanf(line, "%d %d %d %d %d %lf %d %d %d", &prec, &Q, &wg, &half, &sched, &ms, &path, &kb, &shape);
+    if ((got != 6 && got != 8 && got != 9) || prec < 0 || prec >= kPrecisions || shape < 0 || shape > 2 ||
         (Q != 1 && Q != 2 && Q != 4 && Q != 8 && Q != 16) || wg < 0 || wg > 2 || half < 0 || half > 1 ||
         sched < PXD_SCHED_FREQ_MAJOR || sched > PXD_SCHED_SIZE_MAJOR ||
         (path != PXD_PATH_PERSISTENT && path != PXD_PATH_TILED) || (kb != 0 && kb != 64 && kb != 128) ||
@@ -1125,7 +1187,7 @@ int pxd_tune_load(pxd_ctx* ctx, const char* path) {
     }
     Tuning& t = ctx->tuned[prec][size_class(Q)];
     t.wg_per_cu = wg, t.half_sb = half, t.schedule = sched, t.ms = ms, t.valid = true;
-    t.tiled = path == PXD_PATH_TILED, t.tile_kb = kb;
+    t.tiled = path == PXD_PATH_TILED, t.tile_kb = kb, t.tile_shape = shape;
   }
   std::fclose(f);
   return rc;

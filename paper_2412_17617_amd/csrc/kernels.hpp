@@ -188,6 +188,7 @@ struct TlParams {
   TlLayout lay;
   int mixed;            // 0: FP64 augmented [Z_A | V] (eliminate N - P columns), 1: complex64 N x N
   int kb;               // block-column width (64 or 128)
+  int shape;            // output tile of the trailing update: 0 = 128 x 64, 1 = 64 x 64
   int half;             // mixed: operands of the trailing updates (PXD_HALF_*)
   double2* S;           // C x F x P x P
   int* status;          // C x F
@@ -205,7 +206,9 @@ struct TlParams {
 hipError_t tl_gather(hipStream_t s, const TlParams& p, int nmax);
 hipError_t tl_panel(hipStream_t s, const TlParams& p, int K, int nmax);
 hipError_t tl_trsm(hipStream_t s, const TlParams& p, int K, int nmax);
-hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax);
+// trailing update of the columns [Kend + cb, Kend + ce) of every item (Kend the
+// end of the item's block column; ce is clipped to the item's last column)
+hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax, int cb, int ce);
 hipError_t tl_finish(hipStream_t s, const TlParams& p, int nmax);
 hipError_t tl_prepare(const TlParams& p, int nmax);  // kernel attributes (outside capture)
 int tl_max_active();                                 // largest active size the tiled path takes

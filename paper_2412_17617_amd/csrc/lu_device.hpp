@@ -809,6 +809,54 @@ __device__ __forceinline__ void rows_update(const float2* __restrict__ row, int 
     if (jr < P) out[jr] = acc[jr];
 }
 
+// rows_update for two rows at once: both rows' segments are loaded before
+// either is used, so twice the bytes are in flight per thread.
+__device__ __forceinline__ void rows_update2(const float2* __restrict__ rowA, const float2* __restrict__ rowB,
+                                             int kb, const float2* y, float2* outA, float2* outB, int P) {
+  float4 sa[NB / 2], sb[NB / 2];
+  const float4* a4 = reinterpret_cast<const float4*>(rowA);
+  const float4* b4 = reinterpret_cast<const float4*>(rowB);
+  const bool aligned = ((reinterpret_cast<uintptr_t>(rowA) | reinterpret_cast<uintptr_t>(rowB)) & 15) == 0;
+#pragma unroll
+  for (int q = 0; q < NB / 2; ++q) {
+    if (2 * q + 1 < kb && aligned) {
+      sa[q] = a4[q];
+      sb[q] = b4[q];
+    } else {
+      const float2 al = (2 * q < kb) ? rowA[2 * q] : float2{0, 0}, ah = (2 * q + 1 < kb) ? rowA[2 * q + 1] : float2{0, 0};
+      const float2 bl = (2 * q < kb) ? rowB[2 * q] : float2{0, 0}, bh = (2 * q + 1 < kb) ? rowB[2 * q + 1] : float2{0, 0};
+      sa[q] = float4{al.x, al.y, ah.x, ah.y};
+      sb[q] = float4{bl.x, bl.y, bh.x, bh.y};
+    }
+  }
+  float2 accA[4] = {}, accB[4] = {};
+#pragma unroll
+  for (int jr = 0; jr < 4; ++jr)
+    if (jr < P) accA[jr] = outA[jr], accB[jr] = outB[jr];
+#pragma unroll
+  for (int q = 0; q < NB / 2; ++q) {
+    const float2 a0 = float2{sa[q].x, sa[q].y}, a1 = float2{sa[q].z, sa[q].w};
+    const float2 b0 = float2{sb[q].x, sb[q].y}, b1 = float2{sb[q].z, sb[q].w};
+#pragma unroll
+    for (int jr = 0; jr < 4; ++jr)
+      if (jr < P) {
+        if (2 * q < kb) {
+          const float2 yv = y[(2 * q) * P + jr];
+          accA[jr] = cfms(accA[jr], a0, yv);
+          accB[jr] = cfms(accB[jr], b0, yv);
+        }
+        if (2 * q + 1 < kb) {
+          const float2 yv = y[(2 * q + 1) * P + jr];
+          accA[jr] = cfms(accA[jr], a1, yv);
+          accB[jr] = cfms(accB[jr], b1, yv);
+        }
+      }
+  }
+#pragma unroll
+  for (int jr = 0; jr < 4; ++jr)
+    if (jr < P) outA[jr] = accA[jr], outB[jr] = accB[jr];
+}
+
 // Solve (L U) x = P b in complex64 for the P right-hand sides held in LDS
 // (b[row * P + j]), using the factor in W (unit-lower L below the diagonal,
 // U on and above) and the pivots of a factorisation in block columns of
@@ -848,7 +896,13 @@ __device__ __forceinline__ void lu_solve_c64(const float2* __restrict__ W, int l
       }
     }
     __syncthreads();
-    for (int r = k + kb + tid; r < N; r += kThreads) rows_update(W + (size_t)r * ld + k, kb, b + (size_t)k * P, b + (size_t)r * P, P);
+    for (int r = k + kb + tid; r < N; r += 2 * kThreads) {  // two rows per step: both rows' loads in flight
+      if (r + kThreads < N)
+        rows_update2(W + (size_t)r * ld + k, W + (size_t)(r + kThreads) * ld + k, kb, b + (size_t)k * P,
+                     b + (size_t)r * P, b + (size_t)(r + kThreads) * P, P);
+      else
+        rows_update(W + (size_t)r * ld + k, kb, b + (size_t)k * P, b + (size_t)r * P, P);
+    }
     __syncthreads();
   }
   // backward: b <- U^-1 b
@@ -881,7 +935,13 @@ __device__ __forceinline__ void lu_solve_c64(const float2* __restrict__ W, int l
       }
     }
     __syncthreads();
-    for (int r = tid; r < k; r += kThreads) rows_update(W + (size_t)r * ld + k, kb, b + (size_t)k * P, b + (size_t)r * P, P);
+    for (int r = tid; r < k; r += 2 * kThreads) {
+      if (r + kThreads < k)
+        rows_update2(W + (size_t)r * ld + k, W + (size_t)(r + kThreads) * ld + k, kb, b + (size_t)k * P,
+                     b + (size_t)r * P, b + (size_t)(r + kThreads) * P, P);
+      else
+        rows_update(W + (size_t)r * ld + k, kb, b + (size_t)k * P, b + (size_t)r * P, P);
+    }
     __syncthreads();
   }
 }
@@ -889,7 +949,7 @@ __device__ __forceinline__ void lu_solve_c64(const float2* __restrict__ W, int l
 // r = V - Z_A x in FP64, Z_A gathered on the fly from the complex128 parent
 // (with the Z0 loads of the port functions); the result, rounded to
 // complex64, replaces b.  Sixteen lanes per row (four rows per wave), each
-// lane keeping four independent gathers in flight.
+// lane keeping eight independent gathers in flight.
 __device__ __forceinline__ void residual_fp64(const double2* __restrict__ Zf, int M, const int* sI, int N, int P,
                                               const double* __restrict__ plen, double z0,
                                               const double2* __restrict__ x, float2* b) {
@@ -901,12 +961,12 @@ __device__ __forceinline__ void residual_fp64(const double2* __restrict__ Zf, in
     if (i < N) {
       const double2* zrow = Zf + (size_t)sI[i] * M;
       int j = l16;
-      for (; j + 48 < N; j += 64) {
-        double2 z[4];
+      for (; j + 112 < N; j += 128) {  // eight gathers in flight per lane
+        double2 z[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) z[u] = zrow[sI[j + 16 * u]];
+        for (int u = 0; u < 8; ++u) z[u] = zrow[sI[j + 16 * u]];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
           for (int jr = 0; jr < 4; ++jr)
             if (jr < P) {

@@ -21,6 +21,8 @@
 // replay the interchanges block by block), as in the persistent kernels.
 // Then per item: the port block and S (FP64 augmented system) or the
 // complex64 solve with FP64 refinement (mixed modes).
+#include <algorithm>
+
 #include "device.hpp"
 #include "kernels.hpp"
 #include "lu_device.hpp"
@@ -261,16 +263,26 @@ __global__ __launch_bounds__(256) void k_tl_trsm(TlParams p, int K) {
       ci[sn] = acc_t{0, 0, 0, 0};
     }
     const int row = 16 * rs + l16;
-    for (int kq = 0; kq < kpad / 4; ++kq) {
-      const int kk = 4 * kq + lk;
-      const T a = (row < kbb && kk < kbb) ? Li[(size_t)row * kTlKbMax + kk] : T{0, 0};
+    for (int kq0 = 0; kq0 < kpad / 4; kq0 += 8) {
+      // eight k-steps of L11^-1 fragments in flight together
+      T a[8];
 #pragma unroll
-      for (int sn = 0; sn < NSUB; ++sn) {
-        const R br = Br[kk * SBS + 16 * sn + l16], bi = Bi[kk * SBS + 16 * sn + l16];
-        cr[sn] = MF::run(a.x, br, cr[sn]);
-        cr[sn] = MF::run(-a.y, bi, cr[sn]);
-        ci[sn] = MF::run(a.x, bi, ci[sn]);
-        ci[sn] = MF::run(a.y, br, ci[sn]);
+      for (int u = 0; u < 8; ++u) {
+        const int kk = 4 * (kq0 + u) + lk;
+        a[u] = (row < kbb && kk < kbb) ? Li[(size_t)row * kTlKbMax + kk] : T{0, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kk = 4 * (kq0 + u) + lk;
+        if (kq0 + u >= kpad / 4) break;
+#pragma unroll
+        for (int sn = 0; sn < NSUB; ++sn) {
+          const R br = Br[kk * SBS + 16 * sn + l16], bi = Bi[kk * SBS + 16 * sn + l16];
+          cr[sn] = MF::run(a[u].x, br, cr[sn]);
+          ci[sn] = MF::run(a[u].x, bi, ci[sn]);
+          cr[sn] = MF::run(-a[u].y, bi, cr[sn]);
+          ci[sn] = MF::run(a[u].y, br, ci[sn]);
+        }
       }
     }
 #pragma unroll
@@ -291,16 +303,22 @@ __global__ __launch_bounds__(256) void k_tl_trsm(TlParams p, int K) {
 // accumulators).  L21 and U12 are staged in LDS as planar real/imaginary
 // tiles, KC columns of L21 (rows as stored, row stride KC + pad) and KC rows
 // of U12 (row stride TN + 16) at a time; the strides make the fragment reads
-// of a wave hit distinct banks.  The block id is remapped so that the tiles
-// of one item run on one XCD (workgroups are dealt to the XCDs in turn).
-template <typename R, int TM, int TN, int KC>
-__global__ __launch_bounds__(256, 2) void k_tl_update(TlParams p, int K, int tiles_m, int tiles_n) {
+// of a wave hit distinct banks.  The next stage's tiles are fetched into
+// registers while the current stage's MFMAs run, and the four real products
+// of the complex update are issued product by product over all of the
+// wave's tiles, so no MFMA waits on the one before it.  The block id is
+// remapped so that the tiles of one item run on one XCD (workgroups are
+// dealt to the XCDs in turn).
+template <typename R, int TM, int TN, int KC, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_tl_update(TlParams p, int K, int tiles_m, int tiles_n, int cb, int ce) {
   using T = typename Cx<R>::T;
   using MF = Mfma<R>;
   using acc_t = typename MF::acc_t;
   constexpr int WM = TM / 2, WN = TN / 2, SM = WM / 16, SN = WN / 16;
   constexpr int SA = (sizeof(R) == 4) ? KC + 4 : KC + 2;  // A row stride: 4 x odd (f32), 2 x odd (f64)
   constexpr int SBS = TN + 16;
+  constexpr int NA = TM * KC / kThreads, NBV = KC * TN / kThreads;  // stage elements per thread
+  static_assert(TM * KC % kThreads == 0 && KC * TN % kThreads == 0, "stage split");
   __shared__ R Ar[TM * SA], Ai[TM * SA], Br[KC * SBS], Bi[KC * SBS];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -314,10 +332,27 @@ __global__ __launch_bounds__(256, 2) void k_tl_update(TlParams p, int K, int til
   if (K >= t.Ne) return;
   const int kbb = min(p.kb, t.Ne - K), Kend = K + kbb;
   const int tm = tile % tiles_m, tn = tile / tiles_m;
-  const int r0 = Kend + tm * TM, c0 = Kend + tn * TN;
-  if (r0 >= t.N || c0 >= t.ncols) return;
+  const int cend = min(t.ncols, Kend + ce);  // this launch's columns: [Kend + cb, Kend + ce)
+  const int r0 = Kend + tm * TM, c0 = Kend + cb + tn * TN;
+  if (r0 >= t.N || c0 >= cend) return;
   const int ld = p.lay.ld;
   T* W = reinterpret_cast<T*>(p.ws + (size_t)b * p.slot_bytes);
+  T ra[NA], rb[NBV];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
+      const int r = r0 + row, k = k0 + kk;
+      ra[i] = (r < t.N && k < Kend) ? W[(size_t)r * ld + k] : T{0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < NBV; ++i) {
+      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
+      const int k = k0 + kr, cc = c0 + col;
+      rb[i] = (k < Kend && cc < cend) ? W[(size_t)k * ld + cc] : T{0, 0};
+    }
+  };
+  fetch(K);
   const int wm = wid & 1, wn = wid >> 1;
   const int rw = r0 + wm * WM, cw = c0 + wn * WN;
   acc_t cr[SM][SN], ci[SM][SN];
@@ -328,37 +363,35 @@ __global__ __launch_bounds__(256, 2) void k_tl_update(TlParams p, int K, int til
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
-        const T v = (r < t.N && col < t.ncols) ? W[(size_t)r * ld + col] : T{0, 0};
+        const T v = (r < t.N && col < cend) ? W[(size_t)r * ld + col] : T{0, 0};
         cr[a][s][i] = v.x;
         ci[a][s][i] = v.y;
       }
   for (int k0 = K; k0 < Kend; k0 += KC) {
     __syncthreads();  // the previous stage is consumed
-#pragma unroll 2
-    for (int e = tid; e < TM * KC; e += kThreads) {
-      const int row = e / KC, kk = e - row * KC;
-      const int r = r0 + row, k = k0 + kk;
-      const T v = (r < t.N && k < Kend) ? W[(size_t)r * ld + k] : T{0, 0};
-      Ar[row * SA + kk] = v.x;
-      Ai[row * SA + kk] = v.y;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
+      Ar[row * SA + kk] = ra[i].x;
+      Ai[row * SA + kk] = ra[i].y;
     }
-#pragma unroll 2
-    for (int e = tid; e < KC * TN; e += kThreads) {
-      const int kr = e / TN, col = e - kr * TN;
-      const int k = k0 + kr, cc = c0 + col;
-      const T v = (k < Kend && cc < t.ncols) ? W[(size_t)k * ld + cc] : T{0, 0};
-      Br[kr * SBS + col] = v.x;
-      Bi[kr * SBS + col] = v.y;
+#pragma unroll
+    for (int i = 0; i < NBV; ++i) {
+      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
+      Br[kr * SBS + col] = rb[i].x;
+      Bi[kr * SBS + col] = rb[i].y;
     }
     __syncthreads();
+    if (k0 + KC < Kend) fetch(k0 + KC);  // in flight during this stage's products
 #pragma unroll
     for (int kq = 0; kq < KC / 4; ++kq) {
-      R ar[SM], ai[SM], br[SN], bi[SN];
+      R nar[SM], ai[SM], nai[SM], br[SN], bi[SN];
 #pragma unroll
       for (int a = 0; a < SM; ++a) {
         const int row = wm * WM + 16 * a + l16;
-        ar[a] = Ar[row * SA + 4 * kq + lk];
+        nar[a] = -Ar[row * SA + 4 * kq + lk];
         ai[a] = Ai[row * SA + 4 * kq + lk];
+        nai[a] = -ai[a];
       }
 #pragma unroll
       for (int s = 0; s < SN; ++s) {
@@ -366,16 +399,24 @@ __global__ __launch_bounds__(256, 2) void k_tl_update(TlParams p, int K, int til
         br[s] = Br[(4 * kq + lk) * SBS + col];
         bi[s] = Bi[(4 * kq + lk) * SBS + col];
       }
-      // C -= A B:  Cr += (-Ar) Br + Ai Bi,  Ci += (-Ar) Bi + (-Ai) Br
+      // C -= A B:  Cr += (-Ar) Br + Ai Bi,  Ci += (-Ar) Bi + (-Ai) Br,
+      // one real product at a time over every tile of the wave
 #pragma unroll
       for (int a = 0; a < SM; ++a)
 #pragma unroll
-        for (int s = 0; s < SN; ++s) {
-          cr[a][s] = MF::run(-ar[a], br[s], cr[a][s]);
-          cr[a][s] = MF::run(ai[a], bi[s], cr[a][s]);
-          ci[a][s] = MF::run(-ar[a], bi[s], ci[a][s]);
-          ci[a][s] = MF::run(-ai[a], br[s], ci[a][s]);
-        }
+        for (int s = 0; s < SN; ++s) cr[a][s] = MF::run(nar[a], br[s], cr[a][s]);
+#pragma unroll
+      for (int a = 0; a < SM; ++a)
+#pragma unroll
+        for (int s = 0; s < SN; ++s) ci[a][s] = MF::run(nar[a], bi[s], ci[a][s]);
+#pragma unroll
+      for (int a = 0; a < SM; ++a)
+#pragma unroll
+        for (int s = 0; s < SN; ++s) cr[a][s] = MF::run(ai[a], bi[s], cr[a][s]);
+#pragma unroll
+      for (int a = 0; a < SM; ++a)
+#pragma unroll
+        for (int s = 0; s < SN; ++s) ci[a][s] = MF::run(nai[a], br[s], ci[a][s]);
     }
   }
 #pragma unroll
@@ -385,7 +426,7 @@ __global__ __launch_bounds__(256, 2) void k_tl_update(TlParams p, int K, int til
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
-        if (r < t.N && col < t.ncols) W[(size_t)r * ld + col] = T{cr[a][s][i], ci[a][s][i]};
+        if (r < t.N && col < cend) W[(size_t)r * ld + col] = T{cr[a][s][i], ci[a][s][i]};
       }
 }
 
@@ -447,9 +488,28 @@ hipError_t panel_variant(hipStream_t s, const TlParams& p, int K, int q) {
 }
 
 constexpr int kTrsmCols64 = 64, kTrsmCols128 = 32;
-constexpr int kTM64 = 128, kTN64 = 64, kKC64 = 32;
-constexpr int kTM128 = 128, kTN128 = 64, kKC128 = 16;
 
+// Output-tile shapes of the trailing update (TlParams.shape): 0 = 128 x 64 at
+// two workgroups per CU, 1 = 64 x 64 at three (more waves to hide latency,
+// more L21/U12 re-reads).
+template <typename R>
+struct UpdShape;
+template <>
+struct UpdShape<float> {
+  template <int S>
+  static void launch(hipStream_t s, dim3 g, const TlParams& p, int K, int tm, int tn, int cb, int ce) {
+    if (S == 0) hipLaunchKernelGGL((k_tl_update<float, 128, 64, 16, 2>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
+    else hipLaunchKernelGGL((k_tl_update<float, 64, 64, 16, 3>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
+  }
+};
+template <>
+struct UpdShape<double> {
+  template <int S>
+  static void launch(hipStream_t s, dim3 g, const TlParams& p, int K, int tm, int tn, int cb, int ce) {
+    if (S == 0) hipLaunchKernelGGL((k_tl_update<double, 128, 64, 8, 2>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
+    else hipLaunchKernelGGL((k_tl_update<double, 64, 64, 8, 3>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
+  }
+};
 }  // namespace
 
 int tl_max_active() { return 256 * 16; }
@@ -480,16 +540,22 @@ hipError_t tl_trsm(hipStream_t s, const TlParams& p, int K, int nmax) {
   return hipGetLastError();
 }
 
-hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax) {
+hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax, int cb, int ce) {
   const int ncols = p.mixed ? nmax : nmax + p.P;
-  const int mr = nmax - K, nc = ncols - K;  // bounds of every item's trailing block
+  const int mr = nmax - K;                      // bounds of every item's trailing block
+  const int nc = std::min(ncols - K, ce) - cb;  // and of this launch's column range
   if (mr <= 0 || nc <= 0) return hipSuccess;
-  const int TM = p.mixed ? kTM64 : kTM128, TN = p.mixed ? kTN64 : kTN128;
+  const int TM = p.shape == 1 ? 64 : 128, TN = 64;
   const int tiles_m = (mr + TM - 1) / TM, tiles_n = (nc + TN - 1) / TN;
   const int gx = (tiles_m * tiles_n + 7) / 8 * 8;  // a multiple of 8: the XCD grouping needs it
-  const dim3 g(gx, p.B), blk(kThreads);
-  if (p.mixed) hipLaunchKernelGGL((k_tl_update<float, kTM64, kTN64, kKC64>), g, blk, 0, s, p, K, tiles_m, tiles_n);
-  else hipLaunchKernelGGL((k_tl_update<double, kTM128, kTN128, kKC128>), g, blk, 0, s, p, K, tiles_m, tiles_n);
+  const dim3 g(gx, p.B);
+  if (p.mixed) {
+    if (p.shape == 1) UpdShape<float>::launch<1>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+    else UpdShape<float>::launch<0>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+  } else {
+    if (p.shape == 1) UpdShape<double>::launch<1>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+    else UpdShape<double>::launch<0>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+  }
   return hipGetLastError();
 }
 

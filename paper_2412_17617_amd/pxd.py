@@ -44,7 +44,7 @@ class Options(C.Structure):
     _fields_ = [
         ("device", C.c_int32), ("precision", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
         ("wg_per_cu", C.c_int32), ("half_subpanel", C.c_int32), ("schedule", C.c_int32),
-        ("lu_path", C.c_int32), ("tile_kb", C.c_int32), ("ws_gib", C.c_double),
+        ("lu_path", C.c_int32), ("tile_kb", C.c_int32), ("tile_shape", C.c_int32), ("ws_gib", C.c_double),
     ]
 
 
@@ -65,7 +65,8 @@ class Stats(C.Structure):
 
 class TuneEntry(C.Structure):
     _fields_ = [("rows_per_thread", C.c_int32), ("wg_per_cu", C.c_int32), ("half_subpanel", C.c_int32),
-                ("schedule", C.c_int32), ("lu_path", C.c_int32), ("tile_kb", C.c_int32), ("ms", C.c_double)]
+                ("schedule", C.c_int32), ("lu_path", C.c_int32), ("tile_kb", C.c_int32), ("tile_shape", C.c_int32),
+                ("reserved", C.c_int32), ("ms", C.c_double)]
 
 
 _VP = C.c_void_p
@@ -218,9 +219,9 @@ class Evaluator:
     """GPU evaluator context (one per device and host thread)."""
 
     def __init__(self, device=0, precision=PREC_FP64, ir_max_iter=10, ir_tol=1e-7, wg_per_cu=0, half_subpanel=0,
-                 schedule=SCHED_AUTO, lu_path=0, tile_kb=0, ws_gib=0.0):
+                 schedule=SCHED_AUTO, lu_path=0, tile_kb=0, tile_shape=0, ws_gib=0.0):
         o = Options(device, precision, ir_max_iter, ir_tol, wg_per_cu, half_subpanel, schedule, lu_path, tile_kb,
-                    ws_gib)
+                    tile_shape, ws_gib)
         h_ = _VP()
         _check(lib().pxd_create(C.byref(o), C.byref(h_)))
         self._h = h_
@@ -349,10 +350,10 @@ class Evaluator:
         base = np.ascontiguousarray(base_map, np.uint8)
         off = np.ascontiguousarray(offsets, np.int32)
         cl = np.ascontiguousarray(cells, np.int32)
-        rep = (TuneEntry * 16)()
+        rep = (TuneEntry * 64)()
         n = C.c_int32()
         self._c(lib().pxd_autotune(self._h, _ptr(base), len(off) - 1, _ptr(off),
-                                   _ptr(cl if len(cl) else np.zeros(1, np.int32)), n_reps, C.cast(rep, _VP), 16,
+                                   _ptr(cl if len(cl) else np.zeros(1, np.int32)), n_reps, C.cast(rep, _VP), 64,
                                    C.byref(n)))
         return [{k: getattr(rep[i], k) for k, _ in TuneEntry._fields_} for i in range(n.value)]
 

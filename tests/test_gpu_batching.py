@@ -79,21 +79,22 @@ def test_autotune_picks_a_measured_configuration(tmp_path):
     ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_MIXED32)
     rep = ev.autotune(base, off, cells, n_reps=2)
     # persistent path: workgroups per CU x sub-panel width x item order;
-    # tiled path: block-column width x item order
-    assert len(rep) == 12
+    # tiled path: block-column width x update tile x item order
+    assert len(rep) == 16
     assert [r["ms"] for r in rep] == sorted(r["ms"] for r in rep)
     assert all(r["ms"] > 0 for r in rep)
     pers = [r for r in rep if r["lu_path"] == pxd.PATH_PERSISTENT]
     tiled = [r for r in rep if r["lu_path"] == pxd.PATH_TILED]
     assert {(r["wg_per_cu"], r["half_subpanel"], r["schedule"]) for r in pers} == set(
         itertools.product((1, 2), (0, 1), (1, 2)))
-    assert {(r["tile_kb"], r["schedule"]) for r in tiled} == set(itertools.product((64, 128), (1, 2)))
+    assert {(r["tile_kb"], r["tile_shape"], r["schedule"]) for r in tiled} == set(
+        itertools.product((64, 128), (1, 2), (1, 2)))
     path = str(tmp_path / "tune.txt")
     ev.tune_save(path)
     lines = [l.split() for l in open(path) if not l.startswith("#")]
     assert len(lines) == 1 and lines[0][0] == "1"
     assert [int(x) for x in lines[0][2:5]] == [rep[0]["wg_per_cu"], rep[0]["half_subpanel"], rep[0]["schedule"]]
-    assert [int(x) for x in lines[0][6:8]] == [rep[0]["lu_path"], rep[0]["tile_kb"]]
+    assert [int(x) for x in lines[0][6:9]] == [rep[0]["lu_path"], rep[0]["tile_kb"], rep[0]["tile_shape"]]
     # the tuned configuration is used and still matches the oracle
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
@@ -122,7 +123,8 @@ def test_autotune_keeps_fixed_options():
     rep = ev.autotune(base, off, cells)
     pers = [r for r in rep if r["lu_path"] == pxd.PATH_PERSISTENT]
     assert sorted(r["wg_per_cu"] for r in pers) == [1, 2]
-    assert sorted(r["tile_kb"] for r in rep if r["lu_path"] == pxd.PATH_TILED) == [64, 128]
+    assert sorted((r["tile_kb"], r["tile_shape"]) for r in rep if r["lu_path"] == pxd.PATH_TILED) == [
+        (64, 1), (64, 2), (128, 1), (128, 2)]
     assert all(r["half_subpanel"] == 0 and r["schedule"] == pxd.SCHED_FREQ_MAJOR for r in rep)
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
@@ -131,7 +133,8 @@ def test_autotune_keeps_fixed_options():
     # a fixed path and block width leave only the other choices
     ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_FP64, lu_path=pxd.PATH_TILED, tile_kb=128)
     rep = ev.autotune(base, off, cells)
-    assert {(r["lu_path"], r["tile_kb"]) for r in rep} == {(pxd.PATH_TILED, 128)} and len(rep) == 2
+    assert {(r["lu_path"], r["tile_kb"]) for r in rep} == {(pxd.PATH_TILED, 128)} and len(rep) == 4
+    assert {(r["tile_shape"], r["schedule"]) for r in rep} == set(itertools.product((1, 2), (1, 2)))
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     check(S, F, S_o, F_o, pxd.PREC_FP64)
     ev.close()

@@ -38,18 +38,18 @@ def _check_fom(F, F_o, am):
     assert am == best or abs(F_o[am] - F_o[best]) <= FOM_RTOL * F_o[best]
 
 
-@pytest.mark.parametrize("name,prec,kb", [
-    ("tiny4x2", pxd.PREC_FP64, 64), ("tiny4x2", pxd.PREC_MIXED32, 64),
-    ("small6x3", pxd.PREC_FP64, 128), ("small6x3", pxd.PREC_MIXED32, 128),
+@pytest.mark.parametrize("name,prec,kb,shape", [
+    ("tiny4x2", pxd.PREC_FP64, 64, 1), ("tiny4x2", pxd.PREC_MIXED32, 64, 2),
+    ("small6x3", pxd.PREC_FP64, 128, 2), ("small6x3", pxd.PREC_MIXED32, 128, 1),
 ])
-def test_tiled_matches_oracle_and_persistent_path(name, prec, kb):
+def test_tiled_matches_oracle_and_persistent_path(name, prec, kb, shape):
     spec = get_spec(name)
     st, Z, freqs = oracle_parent(spec)
     base = spec.base_map()
     off, cells = spec.flips()
-    print(f"{name} precision {prec} block columns {kb}", flush=True)
+    print(f"{name} precision {prec} block columns {kb} update tile {shape}", flush=True)
     S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
-    ev, _ = make_evaluator(spec, Z, freqs, precision=prec, lu_path=pxd.PATH_TILED, tile_kb=kb)
+    ev, _ = make_evaluator(spec, Z, freqs, precision=prec, lu_path=pxd.PATH_TILED, tile_kb=kb, tile_shape=shape)
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     stats = ev.stats()
     ev.close()
@@ -66,9 +66,10 @@ def test_tiled_matches_oracle_and_persistent_path(name, prec, kb):
         assert stats["fallbacks"] == 0 and stats["ir_iterations"] >= stats["items"]
 
 
+@pytest.mark.parametrize("shape", [1, 2])
 @pytest.mark.parametrize("prec", [pxd.PREC_FP64, pxd.PREC_MIXED32])
 @pytest.mark.parametrize("nx,layers,p", [(11, 2, 0.6), (16, 2, 0.7), (26, 1, 0.9)])
-def test_tiled_sizes_span_several_tiles(prec, nx, layers, p):
+def test_tiled_sizes_span_several_tiles(prec, nx, layers, p, shape):
     """Active sizes ~150-700: one to six 128-row output tiles, several block
     columns, ragged last tiles; one frequency."""
     ports = (PortSpec("right", 0), PortSpec("top", 0), PortSpec("left", layers - 1))
@@ -78,8 +79,8 @@ def test_tiled_sizes_span_several_tiles(prec, nx, layers, p):
     base = spec.base_map()
     off, cells = single_flips(np.arange(0, spec.n_cells, max(1, spec.n_cells // 6))[:6])
     S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
-    ev, _ = make_evaluator(spec, Z, freqs, precision=prec, lu_path=pxd.PATH_TILED)
-    print(f"nx {nx} layers {layers} precision {prec}", flush=True)
+    ev, _ = make_evaluator(spec, Z, freqs, precision=prec, lu_path=pxd.PATH_TILED, tile_shape=shape)
+    print(f"nx {nx} layers {layers} precision {prec} update tile {shape}", flush=True)
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     stats = ev.stats()
     ev.close()
