@@ -73,6 +73,10 @@ extern "C" {
 #define PXD_PREC_MIXED32 1 /* complex64 LU + FP64 residual and iterative refinement */
 #define PXD_PREC_MIXED_BF16 2 /* as MIXED32, the rank-64 block-column updates on BF16 operands (FP32 accumulation) */
 #define PXD_PREC_MIXED_F16 3  /* as MIXED32, the rank-64 block-column updates on FP16 operands (FP32 accumulation) */
+/* as MIXED32, the trailing updates on split BF16 operands: x = hi + lo (both BF16), each real product as
+ * hi*hi + hi*lo + lo*hi on the BF16 MFMA with FP32 accumulation (~2^-16 relative, FP32's exponent range);
+ * tiled LU.  The plain BF16 and FP16 modes run on the persistent LU only (active sizes up to 2,048). */
+#define PXD_PREC_MIXED_BF16X3 4
 
 /* ---------------------------------------------------------------- structure */
 

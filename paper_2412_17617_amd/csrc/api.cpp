@@ -63,7 +63,7 @@ struct Tuning {
   double ms = 0;
 };
 constexpr int kSizeClasses = 5;  // Q = 1, 2, 4, 8, 16 (active sizes up to 256 Q)
-constexpr int kPrecisions = 4;   // PXD_PREC_*
+constexpr int kPrecisions = 5;   // PXD_PREC_*
 constexpr int kClassQ[kSizeClasses] = {1, 2, 4, 8, 16};
 int size_class(int Q) { return Q <= 1 ? 0 : Q <= 2 ? 1 : Q <= 4 ? 2 : Q <= 8 ? 3 : 4; }
 
@@ -175,7 +175,10 @@ struct Arena {
 // tuned choice for the size class, else tiled only above the persistent
 // kernels' 2,048 limit.
 bool use_tiled(const pxd_ctx* ctx, int nmax) {
-  const bool no_c64 = ctx->opt.precision != PXD_PREC_FP64 && !ctx->Z64.p;
+  const int prec = ctx->opt.precision;
+  if (prec == PXD_PREC_MIXED_BF16X3) return true;  // split-BF16 updates exist on the tiled path only
+  if (prec == PXD_PREC_MIXED_BF16 || prec == PXD_PREC_MIXED_F16) return false;  // plain ones on the persistent
+  const bool no_c64 = prec != PXD_PREC_FP64 && !ctx->Z64.p;
   if (ctx->opt.lu_path == PXD_PATH_TILED || nmax > 2048 || no_c64) return true;
   if (ctx->opt.lu_path == PXD_PATH_PERSISTENT) return false;
   if (ctx->forced) return ctx->forced->tiled;
@@ -269,8 +272,7 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
   tp.mixed = mixed ? 1 : 0;
   tp.kb = kb;
   tp.shape = tile_shape(ctx, nmax_all) - 1;
-  tp.half = ctx->opt.precision == PXD_PREC_MIXED_BF16 ? PXD_HALF_BF16
-            : ctx->opt.precision == PXD_PREC_MIXED_F16 ? PXD_HALF_F16 : PXD_HALF_NONE;
+  tp.half = ctx->opt.precision == PXD_PREC_MIXED_BF16X3 ? PXD_HALF_BF16 : PXD_HALF_NONE;  // split products
   tp.S = d_S;
   tp.status = item_status;
   tp.fallback_mode = fallback_mode ? 1 : 0;
@@ -451,7 +453,11 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
     return evaluate_tiled(ctx, b, s, C, Nc, Ilist, cnt, item_status, fb_list, d_S, d_fom, d_cand_status, d_argmin,
                           nmin, nmax);
   }
-  if (nmax > 2048) return ctx->fail(PXD_ESHAPE, "active size above 2048 needs the tiled LU (lu_path)");
+  if (nmax > 2048)
+    return ctx->fail(PXD_ESHAPE, "active size above 2,048: the plain BF16 and FP16 modes run on the persistent LU "
+                                 "only (use PXD_PREC_MIXED32 or PXD_PREC_MIXED_BF16X3)");
+  if (mixed && !ctx->Z64.p)
+    return ctx->fail(PXD_ENOMEM, "the plain BF16 and FP16 modes need the complex64 parent copy, which did not fit");
   if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
 
   const Tuning tune = resolve(ctx, pxd::rows_per_thread(nmax));
@@ -772,7 +778,7 @@ int pxd_create(const pxd_options* opt, pxd_ctx** out) {
   if (opt) ctx->opt = *opt;
   if (ctx->opt.ir_max_iter <= 0) ctx->opt.ir_max_iter = 10;
   if (!(ctx->opt.ir_tol > 0)) ctx->opt.ir_tol = 1e-7;
-  if (ctx->opt.precision < PXD_PREC_FP64 || ctx->opt.precision > PXD_PREC_MIXED_F16) {
+  if (ctx->opt.precision < PXD_PREC_FP64 || ctx->opt.precision > PXD_PREC_MIXED_BF16X3) {
     delete ctx;
     return pxd::set_thread_error(PXD_EINVAL, "unknown precision mode");
   }
@@ -1096,9 +1102,13 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
     if (rc) return rc;
     nmax_batch = *std::max_element(Nb.begin(), Nb.end());
   }
-  const bool no_c64 = ctx->opt.precision != PXD_PREC_FP64 && !ctx->Z64.p;
-  const bool try_persistent = ctx->opt.lu_path != PXD_PATH_TILED && nmax_batch <= 2048 && !no_c64;
-  const bool try_tiled = ctx->opt.lu_path != PXD_PATH_PERSISTENT;
+  const int prec = ctx->opt.precision;
+  const bool no_c64 = prec != PXD_PREC_FP64 && !ctx->Z64.p;
+  const bool plain_half = prec == PXD_PREC_MIXED_BF16 || prec == PXD_PREC_MIXED_F16;
+  const bool try_persistent = ctx->opt.lu_path != PXD_PATH_TILED && nmax_batch <= 2048 && !no_c64 &&
+                              prec != PXD_PREC_MIXED_BF16X3;
+  const bool try_tiled = ctx->opt.lu_path != PXD_PATH_PERSISTENT && !plain_half;
+  if (!try_persistent && !try_tiled) return ctx->fail(PXD_ESHAPE, "no LU path takes this batch in this precision");
   std::vector<Tuning> cands;
   if (try_persistent)
     for (int wg = wg_hi; wg >= wg_lo; --wg)

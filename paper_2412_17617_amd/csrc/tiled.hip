@@ -430,6 +430,138 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update(TlParams p, int K, int t
       }
 }
 
+// Split-BF16 form of the complex64 trailing update (PXD_PREC_MIXED_BF16):
+// every operand x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), each
+// real product X Y as Xh Yh + Xh Yl + Xl Yh on the 16x16x16 BF16 MFMA with
+// FP32 accumulation (the dropped Xl Yl is ~2^-16 relative).  BF16 keeps
+// FP32's exponent range, so no scaling is needed.  A stage is one 16-wide
+// k-chunk: L21 and U12 are split once when staged, into hi/lo planes of the
+// real and imaginary parts, L21 as [row][k] and U12 transposed as [col][k]
+// so that every fragment is four consecutive k of one row or column (one
+// 8-byte LDS read; row stride 24 keeps a wave's reads on distinct banks).
+template <int TM, int TN, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K, int tiles_m, int tiles_n, int cb,
+                                                               int ce) {
+  using T = float2;
+  using HM = Half<PXD_HALF_BF16>;
+  using v4 = typename HM::v4;
+  using MF = Mfma<float>;
+  constexpr int KC = 16, S16 = 24;
+  constexpr int WM = TM / 2, WN = TN / 2, SM = WM / 16, SN = WN / 16;
+  constexpr int NA = TM * KC / kThreads, NBV = KC * TN / kThreads;
+  static_assert(TM * KC % kThreads == 0 && KC * TN % kThreads == 0, "stage split");
+  // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+  __shared__ __align__(16) short As[4][TM * S16], Bs[4][TN * S16];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int total = gridDim.x * gridDim.y;
+  const int lid = blockIdx.x + blockIdx.y * gridDim.x;
+  const int gid = (lid & 7) * (total >> 3) + (lid >> 3);
+  const int b = gid / gridDim.x, tile = gid - b * gridDim.x;
+  if (b >= p.B || tile >= tiles_m * tiles_n) return;
+  const TlItem t = tl_item(p, b);
+  if (K >= t.Ne) return;
+  const int kbb = min(p.kb, t.Ne - K), Kend = K + kbb;
+  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  const int cend = min(t.ncols, Kend + ce);
+  const int r0 = Kend + tm * TM, c0 = Kend + cb + tn * TN;
+  if (r0 >= t.N || c0 >= cend) return;
+  const int ld = p.lay.ld;
+  T* W = reinterpret_cast<T*>(p.ws + (size_t)b * p.slot_bytes);
+  T ra[NA], rb[NBV];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
+      const int r = r0 + row, k = k0 + kk;
+      ra[i] = (r < t.N && k < Kend) ? W[(size_t)r * ld + k] : T{0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < NBV; ++i) {
+      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
+      const int k = k0 + kr, cc = c0 + col;
+      rb[i] = (k < Kend && cc < cend) ? W[(size_t)k * ld + cc] : T{0, 0};
+    }
+  };
+  auto split = [](float x, short& hi, short& lo) {
+    hi = HM::one(x);
+    lo = HM::one(x - __uint_as_float((unsigned)(unsigned short)hi << 16));
+  };
+  fetch(K);
+  const int wm = wid & 1, wn = wid >> 1;
+  const int rw = r0 + wm * WM, cw = c0 + wn * WN;
+  fx4 cr[SM][SN], ci[SM][SN];
+#pragma unroll
+  for (int a = 0; a < SM; ++a)
+#pragma unroll
+    for (int s = 0; s < SN; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
+        const T v = (r < t.N && col < cend) ? W[(size_t)r * ld + col] : T{0, 0};
+        cr[a][s][i] = v.x;
+        ci[a][s][i] = v.y;
+      }
+  for (int k0 = K; k0 < Kend; k0 += KC) {
+    __syncthreads();  // the previous stage is consumed
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
+      split(ra[i].x, As[0][row * S16 + kk], As[1][row * S16 + kk]);
+      split(ra[i].y, As[2][row * S16 + kk], As[3][row * S16 + kk]);
+    }
+#pragma unroll
+    for (int i = 0; i < NBV; ++i) {
+      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
+      split(rb[i].x, Bs[0][col * S16 + kr], Bs[1][col * S16 + kr]);
+      split(rb[i].y, Bs[2][col * S16 + kr], Bs[3][col * S16 + kr]);
+    }
+    __syncthreads();
+    if (k0 + KC < Kend) fetch(k0 + KC);  // in flight during this stage's products
+    v4 fa[4][SM], fb[4][SN];  // fragments per plane
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int a = 0; a < SM; ++a)
+        fa[q][a] = *reinterpret_cast<const v4*>(&As[q][(wm * WM + 16 * a + l16) * S16 + 4 * lk]);
+#pragma unroll
+      for (int s = 0; s < SN; ++s)
+        fb[q][s] = *reinterpret_cast<const v4*>(&Bs[q][(wn * WN + 16 * s + l16) * S16 + 4 * lk]);
+    }
+    v4 nah[SM], nal[SM], naih[SM], nail[SM];  // -Ar and -Ai (sign bits flipped)
+#pragma unroll
+    for (int a = 0; a < SM; ++a) {
+      nah[a] = fa[0][a] ^ (short)0x8000;
+      nal[a] = fa[1][a] ^ (short)0x8000;
+      naih[a] = fa[2][a] ^ (short)0x8000;
+      nail[a] = fa[3][a] ^ (short)0x8000;
+    }
+    // Cr += (-Ar) Br + Ai Bi,  Ci += (-Ar) Bi + (-Ai) Br, each product in
+    // three parts, issued part by part over all of the wave's tiles
+#define PXD_SPLIT3(ACC, XH, XL, YH, YL)                                                    \
+  _Pragma("unroll") for (int a = 0; a < SM; ++a) _Pragma("unroll") for (int s = 0; s < SN; ++s) \
+      ACC[a][s] = HM::run(XH[a], YH[s], ACC[a][s]);                                      \
+  _Pragma("unroll") for (int a = 0; a < SM; ++a) _Pragma("unroll") for (int s = 0; s < SN; ++s) \
+      ACC[a][s] = HM::run(XH[a], YL[s], ACC[a][s]);                                      \
+  _Pragma("unroll") for (int a = 0; a < SM; ++a) _Pragma("unroll") for (int s = 0; s < SN; ++s) \
+      ACC[a][s] = HM::run(XL[a], YH[s], ACC[a][s]);
+    PXD_SPLIT3(cr, nah, nal, fb[0], fb[1])
+    PXD_SPLIT3(ci, nah, nal, fb[2], fb[3])
+    PXD_SPLIT3(cr, fa[2], fa[3], fb[2], fb[3])
+    PXD_SPLIT3(ci, naih, nail, fb[0], fb[1])
+#undef PXD_SPLIT3
+  }
+#pragma unroll
+  for (int a = 0; a < SM; ++a)
+#pragma unroll
+    for (int s = 0; s < SN; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
+        if (r < t.N && col < cend) W[(size_t)r * ld + col] = T{cr[a][s][i], ci[a][s][i]};
+      }
+}
+
 // ------------------------------------------------------------------ per-item finish
 
 // FP64 augmented system: the P x P port block left after eliminating the
@@ -549,7 +681,12 @@ hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax, int cb, 
   const int tiles_m = (mr + TM - 1) / TM, tiles_n = (nc + TN - 1) / TN;
   const int gx = (tiles_m * tiles_n + 7) / 8 * 8;  // a multiple of 8: the XCD grouping needs it
   const dim3 g(gx, p.B);
-  if (p.mixed) {
+  if (p.mixed && p.half == PXD_HALF_BF16) {
+    if (p.shape == 1)
+      hipLaunchKernelGGL((k_tl_update_bf16x3<64, 64, 3>), g, dim3(kThreads), 0, s, p, K, tiles_m, tiles_n, cb, ce);
+    else
+      hipLaunchKernelGGL((k_tl_update_bf16x3<128, 64, 2>), g, dim3(kThreads), 0, s, p, K, tiles_m, tiles_n, cb, ce);
+  } else if (p.mixed) {
     if (p.shape == 1) UpdShape<float>::launch<1>(s, g, p, K, tiles_m, tiles_n, cb, ce);
     else UpdShape<float>::launch<0>(s, g, p, K, tiles_m, tiles_n, cb, ce);
   } else {

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PXD_LIB_PATH") or os.path.join(_HERE, "libpxd.so")
 
 OK, EINVAL, ENOMEM, ENOTLOADED, EDEVICE, ESHAPE = 0, -1, -2, -3, -4, -5
-PREC_FP64, PREC_MIXED32, PREC_MIXED_BF16, PREC_MIXED_F16 = 0, 1, 2, 3
+PREC_FP64, PREC_MIXED32, PREC_MIXED_BF16, PREC_MIXED_F16, PREC_MIXED_BF16X3 = 0, 1, 2, 3, 4
 KIND_ALWAYS, KIND_INNER, KIND_INTER, KIND_PIXPORT, KIND_VIA = 0, 1, 2, 3, 4
 STATUS_OK, STATUS_FALLBACK, STATUS_NONFINITE, STATUS_SINGULAR, STATUS_SIZE = 0, 1, -1, -2, -3
 SCHED_AUTO, SCHED_FREQ_MAJOR, SCHED_SIZE_MAJOR = 0, 1, 2

@@ -161,3 +161,47 @@ def test_ceiling32_sampled_against_oracle():
     for prec, (S, status, dS) in r.items():
         assert np.all((status == 0) | (status == 1))
         assert dS <= S_TOL[prec]
+
+
+@pytest.mark.parametrize("name,nx,layers", [("tiny4x2", 4, 2), ("tiny4x2", 16, 2)])
+def test_split_bf16_updates(name, nx, layers):
+    """PXD_PREC_MIXED_BF16X3: trailing updates on split BF16 operands (three
+    products, ~2^-16 relative), then FP64 refinement.  Every result meets the
+    oracle to the mixed bar; on these small, well-conditioned systems the
+    split factor settles on its own for most items (no FP64 hand-off)."""
+    ports = (PortSpec("right", 0), PortSpec("top", 0), PortSpec("left", layers - 1))
+    spec = spec_variant(name, nx=nx, ny=nx, n_layers=layers, density=0.7, n_vias=3, ports=ports, seed=60 + nx)
+    st, Z, freqs = oracle_parent(spec, (1,))
+    base = spec.base_map()
+    off, cells = single_flips(np.arange(0, spec.n_cells, max(1, spec.n_cells // 6))[:6])
+    S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
+    ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_MIXED_BF16X3, ir_max_iter=30)
+    print(f"split BF16 nx {nx}", flush=True)
+    S, F, status, am = ev.evaluate_flips(base, off, cells)
+    stats = ev.stats()
+    ev.close()
+    print(f"  N {stats['max_active']}: {stats['ir_iterations']} refinement steps, {stats['fallbacks']} of "
+          f"{stats['items']} items to FP64, max |dS| {np.abs(S - S_o).max():.2e}", flush=True)
+    assert np.all((status == pxd.STATUS_OK) | (status == pxd.STATUS_FALLBACK))
+    assert np.abs(S - S_o).max() <= 1e-4
+    _check_fom(F, F_o, am)
+    assert 2 * stats["fallbacks"] <= stats["items"], stats
+
+
+def test_plain_half_modes_above_2048_are_refused():
+    """The plain BF16 / FP16 block-update modes exist on the persistent LU
+    only; a batch above its 2,048 limit is refused, not run in another
+    arithmetic."""
+    g = np.load(os.path.join(GOLD, "large_dense24.npz"))
+    spec = spec_variant("stress24", density=float(g["density"]))
+    pb = pxd.Problem.from_spec(spec)
+    off, cells = single_flips([0])
+    for prec in (pxd.PREC_MIXED_BF16, pxd.PREC_MIXED_F16):
+        ev = pxd.Evaluator(precision=prec)
+        ev.load_problem(pb, spec.z0)
+        ev.load_parent(np.zeros((1, pb.M, pb.M), np.complex128), spec.freqs[:1])
+        ev.set_fom_paper()
+        with pytest.raises(pxd.PxdError) as e:
+            ev.evaluate_flips(spec.base_map(), off, cells)
+        assert e.value.code == pxd.ESHAPE
+        ev.close()
