@@ -188,6 +188,8 @@ typedef struct pxd_stats {
   double ms_update;       /* ... their summed duration (an event pair around each launch) */
   double update_gflop;    /* ... their algorithmic work: 8 kb (N - Kend)(ncols - Kend) real flops per item
                              and block column (complex multiply-add = 8 flops) */
+  double update_gbyte;    /* ... and their algorithmic memory traffic: the trailing block read and written
+                             once, L21 and U12 read once (bytes per complex entry 8 or 16) */
 } pxd_stats;
 
 int pxd_create(const pxd_options* opt, pxd_ctx** out);

@@ -103,7 +103,7 @@ struct pxd_ctx {
   bool profile = false;
   std::vector<hipEvent_t> upd_ev;
   int n_upd = 0;
-  double upd_flops = 0;
+  double upd_flops = 0, upd_bytes = 0;
   // tiled path: item order of the call (host copy) and its device copy
   std::vector<int> h_items, h_fb;
   DevBuf tl_items;
@@ -231,7 +231,11 @@ int tiled_update(pxd_ctx* ctx, hipStream_t s, const pxd::TlParams& tp, const std
     if (K >= Ne) continue;
     const int kend = K + std::min(kb, Ne - K);
     const long long c_lo = kend + (long long)cb, c_hi = std::min<long long>(nc, kend + (long long)ce);
-    if (c_hi > c_lo) ctx->upd_flops += 8.0 * (kend - K) * (double)(N - kend) * (double)(c_hi - c_lo);
+    if (c_hi > c_lo) {
+      const double kk = kend - K, m = N - kend, n = (double)(c_hi - c_lo), es = mixed ? 8.0 : 16.0;
+      ctx->upd_flops += 8.0 * kk * m * n;
+      ctx->upd_bytes += es * (2.0 * m * n + kk * m + kk * n);  // C read and written, L21 and U12 read once
+    }
   }
   HIPCHK(ctx, hipEventRecord(ctx->upd_ev[2 * ctx->n_upd], s));
   HIPCHK(ctx, pxd::tl_update(s, tp, K, nmax, cb, ce));
@@ -393,7 +397,7 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
   const bool events = !capturing;
   const int M = ctx->M, F = ctx->F, P = ctx->P;
   if (events) ctx->stats = pxd_stats{}, ctx->stats_lowrank = false;
-  ctx->n_upd = 0, ctx->upd_flops = 0;
+  ctx->n_upd = 0, ctx->upd_flops = 0, ctx->upd_bytes = 0;
   if (C == 0) return PXD_OK;
   const long long items = (long long)C * F;
   int *Nc, *Ilist, *order, *cnt, *item_status, *fb_list = nullptr, *minmax = nullptr;
@@ -1362,6 +1366,7 @@ int pxd_get_stats(const pxd_ctx* ctx, pxd_stats* out) {
     if (hipEventElapsedTime(&c, ctx->ev[3], ctx->ev[4]) == hipSuccess) out->ms_fom = c;
     out->update_launches = ctx->n_upd;
     out->update_gflop = ctx->upd_flops / 1e9;
+    out->update_gbyte = ctx->upd_bytes / 1e9;
     for (int i = 0; i < ctx->n_upd; ++i) {
       float u = 0;
       if (hipEventElapsedTime(&u, ctx->upd_ev[2 * i], ctx->upd_ev[2 * i + 1]) == hipSuccess) out->ms_update += u;

@@ -59,7 +59,7 @@ class Stats(C.Structure):
         ("max_active", C.c_int32), ("min_active", C.c_int32),
         ("ms_expand", C.c_double), ("ms_solve", C.c_double), ("ms_fallback", C.c_double), ("ms_fom", C.c_double),
         ("ms_base_inverse", C.c_double), ("base_reused", C.c_int32), ("update_launches", C.c_int32),
-        ("ms_update", C.c_double), ("update_gflop", C.c_double),
+        ("ms_update", C.c_double), ("update_gflop", C.c_double), ("update_gbyte", C.c_double),
     ]
 
 
