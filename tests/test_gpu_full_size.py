@@ -85,3 +85,39 @@ def test_active_size_above_the_tiled_limit_is_refused():
         ev.evaluate_flips(np.ones(spec.n_cells, np.uint8), off, np.zeros(0, np.int32))
     assert e.value.code == pxd.ESHAPE
     ev.close()
+
+
+def test_batched20_uneven_batch_at_size():
+    """The 20 x 20 x 2 uneven batch (8 maps of density 0.55 ... 0.83, 100
+    single flips each: 800 whole maps, active sizes ~915-1,740) in one call
+    at one frequency of the first passband, in FP64 and complex64 + FP64
+    refinement (the library picks the LU path per the autotuned table or
+    its defaults); a seeded sample of 8 maps solved by the oracle."""
+    spec = get_spec("batched20")
+    fi = int(np.argmin(np.abs(spec.freqs - 5.5e9)))
+    freqs = spec.freqs[fi:fi + 1]
+    st = geometry.build_structure(spec)
+    Z = efie.fill(st, freqs[0])[None]
+    maps = spec.uneven_maps()
+    pick = np.sort(permutation(len(maps), 79)[:8])
+    pl = search.port_lengths(st)
+    S_o = {}
+    for c in pick:
+        sel = st.active(maps[c])
+        S_o[c] = network.s_parameters(network.reduce_matrix(Z[0], sel), network.port_positions(sel, st.port_bf), pl,
+                                      spec.z0)
+    pb = pxd.Problem.from_spec(spec)
+    for prec, tol in ((pxd.PREC_FP64, 1e-10), (pxd.PREC_MIXED32, 1e-4)):
+        ev = pxd.Evaluator(precision=prec, ir_max_iter=40)
+        ev.load_parent(Z, freqs)
+        ev.load_problem(pb, spec.z0)
+        ev.set_fom_paper()
+        S, F, status, am = ev.evaluate_maps(maps)
+        stats = ev.stats()
+        ev.close()
+        dS = max(np.abs(S[c, 0] - S_o[c]).max() for c in pick)
+        print(f"uneven batch precision {prec}: N {stats['min_active']}-{stats['max_active']}, {len(maps)} maps, "
+              f"sampled max |dS| {dS:.2e}, {stats['fallbacks']} fallbacks", flush=True)
+        assert stats["min_active"] < 1100 and 1600 < stats["max_active"] <= 2048
+        assert np.all((status == 0) | (status == 1))
+        assert dS <= tol
