@@ -410,11 +410,8 @@ __device__ __forceinline__ void trailing_update(typename Cx<R>::T* __restrict__ 
         for (int b = 0; b < 2; ++b)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int r = r0 + 32 * tm + 16 * a + MF::row(lane, i);
-            const int col = c0 + 32 * tn + 16 * b + l16;
-            const T v = (r < N && col < ncols) ? W[(size_t)r * ld + col] : T{0, 0};
-            cr[a][b][i] = v.x;
-            ci[a][b][i] = v.y;
+            cr[a][b][i] = R(0);  // the products are summed apart from C (one rounding into C)
+            ci[a][b][i] = R(0);
           }
       auto load_b = [&](int kq, int b) -> T {
         const int kk = 4 * kq + lk;
@@ -467,7 +464,10 @@ __device__ __forceinline__ void trailing_update(typename Cx<R>::T* __restrict__ 
           for (int i = 0; i < 4; ++i) {
             const int r = r0 + 32 * tm + 16 * a + MF::row(lane, i);
             const int col = c0 + 32 * tn + 16 * b + l16;
-            if (r < N && col < ncols) W[(size_t)r * ld + col] = T{cr[a][b][i], ci[a][b][i]};
+            if (r < N && col < ncols) {
+              const T v = W[(size_t)r * ld + col];
+              W[(size_t)r * ld + col] = T{v.x + cr[a][b][i], v.y + ci[a][b][i]};
+            }
           }
     }
   }
@@ -517,10 +517,8 @@ __device__ __forceinline__ void wide_update(typename Cx<R>::T* __restrict__ W, i
           for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int r = rb + 16 * t + MF::row(lane, i), col = s0 + 16 * b + l16;
-              const T v = (r < r1 && col < c1) ? W[(size_t)r * ld + col] : T{0, 0};
-              cr[t][b][i] = v.x;
-              ci[t][b][i] = v.y;
+              cr[t][b][i] = 0;  // the products are summed apart from C (one rounding into C)
+              ci[t][b][i] = 0;
             }
 #pragma unroll
         for (int kq = 0; kq < KQ; ++kq) {
@@ -546,7 +544,10 @@ __device__ __forceinline__ void wide_update(typename Cx<R>::T* __restrict__ W, i
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int r = rb + 16 * t + MF::row(lane, i), col = s0 + 16 * b + l16;
-              if (r < r1 && col < c1) W[(size_t)r * ld + col] = T{cr[t][b][i], ci[t][b][i]};
+              if (r < r1 && col < c1) {
+                const T v = W[(size_t)r * ld + col];
+                W[(size_t)r * ld + col] = T{v.x + cr[t][b][i], v.y + ci[t][b][i]};
+              }
             }
       }
     }
@@ -622,10 +623,8 @@ __device__ __forceinline__ void wide_update_half(float2* __restrict__ W, int ld,
           for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int r = rb + 16 * t + MF::row(lane, i), col = s0 + 16 * b + l16;
-              const float2 v = (r < r1 && col < c1) ? W[(size_t)r * ld + col] : float2{0, 0};
-              cr[t][b][i] = v.x;
-              ci[t][b][i] = v.y;
+              cr[t][b][i] = 0;  // the products are summed apart from C (one rounding into C)
+              ci[t][b][i] = 0;
             }
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
@@ -658,7 +657,10 @@ __device__ __forceinline__ void wide_update_half(float2* __restrict__ W, int ld,
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int r = rb + 16 * t + MF::row(lane, i), col = s0 + 16 * b + l16;
-              if (r < r1 && col < c1) W[(size_t)r * ld + col] = float2{cr[t][b][i], ci[t][b][i]};
+              if (r < r1 && col < c1) {
+                const float2 v = W[(size_t)r * ld + col];
+                W[(size_t)r * ld + col] = float2{v.x + cr[t][b][i], v.y + ci[t][b][i]};
+              }
             }
       }
     }
@@ -790,10 +792,7 @@ __device__ __forceinline__ void rows_update(const float2* __restrict__ row, int 
       seg[q] = float4{lo.x, lo.y, hi.x, hi.y};
     }
   }
-  float2 acc[4] = {};
-#pragma unroll
-  for (int jr = 0; jr < 4; ++jr)
-    if (jr < P) acc[jr] = out[jr];
+  float2 acc[4] = {};  // the products are summed apart from out (one rounding into it)
 #pragma unroll
   for (int q = 0; q < NB / 2; ++q) {
     const float2 l0 = float2{seg[q].x, seg[q].y}, l1 = float2{seg[q].z, seg[q].w};
@@ -806,7 +805,7 @@ __device__ __forceinline__ void rows_update(const float2* __restrict__ row, int 
   }
 #pragma unroll
   for (int jr = 0; jr < 4; ++jr)
-    if (jr < P) out[jr] = acc[jr];
+    if (jr < P) out[jr] = float2{out[jr].x + acc[jr].x, out[jr].y + acc[jr].y};
 }
 
 // rows_update for two rows at once: both rows' segments are loaded before
@@ -829,10 +828,7 @@ __device__ __forceinline__ void rows_update2(const float2* __restrict__ rowA, co
       sb[q] = float4{bl.x, bl.y, bh.x, bh.y};
     }
   }
-  float2 accA[4] = {}, accB[4] = {};
-#pragma unroll
-  for (int jr = 0; jr < 4; ++jr)
-    if (jr < P) accA[jr] = outA[jr], accB[jr] = outB[jr];
+  float2 accA[4] = {}, accB[4] = {};  // summed apart from outA, outB
 #pragma unroll
   for (int q = 0; q < NB / 2; ++q) {
     const float2 a0 = float2{sa[q].x, sa[q].y}, a1 = float2{sa[q].z, sa[q].w};
@@ -854,7 +850,10 @@ __device__ __forceinline__ void rows_update2(const float2* __restrict__ rowA, co
   }
 #pragma unroll
   for (int jr = 0; jr < 4; ++jr)
-    if (jr < P) outA[jr] = accA[jr], outB[jr] = accB[jr];
+    if (jr < P) {
+      outA[jr] = float2{outA[jr].x + accA[jr].x, outA[jr].y + accA[jr].y};
+      outB[jr] = float2{outB[jr].x + accB[jr].x, outB[jr].y + accB[jr].y};
+    }
 }
 
 // Solve (L U) x = P b in complex64 for the P right-hand sides held in LDS

@@ -362,10 +362,8 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update(TlParams p, int K, int t
     for (int s = 0; s < SN; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
-        const T v = (r < t.N && col < cend) ? W[(size_t)r * ld + col] : T{0, 0};
-        cr[a][s][i] = v.x;
-        ci[a][s][i] = v.y;
+        cr[a][s][i] = 0;  // the products are summed apart from C (one rounding into C)
+        ci[a][s][i] = 0;
       }
   for (int k0 = K; k0 < Kend; k0 += KC) {
     __syncthreads();  // the previous stage is consumed
@@ -426,7 +424,10 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update(TlParams p, int K, int t
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
-        if (r < t.N && col < cend) W[(size_t)r * ld + col] = T{cr[a][s][i], ci[a][s][i]};
+        if (r < t.N && col < cend) {
+          const T v = W[(size_t)r * ld + col];
+          W[(size_t)r * ld + col] = T{v.x + cr[a][s][i], v.y + ci[a][s][i]};
+        }
       }
 }
 
@@ -497,10 +498,8 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
     for (int s = 0; s < SN; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
-        const T v = (r < t.N && col < cend) ? W[(size_t)r * ld + col] : T{0, 0};
-        cr[a][s][i] = v.x;
-        ci[a][s][i] = v.y;
+        cr[a][s][i] = 0;  // the products are summed apart from C (one rounding into C)
+        ci[a][s][i] = 0;
       }
   for (int k0 = K; k0 < Kend; k0 += KC) {
     __syncthreads();  // the previous stage is consumed
@@ -558,7 +557,10 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
-        if (r < t.N && col < cend) W[(size_t)r * ld + col] = T{cr[a][s][i], ci[a][s][i]};
+        if (r < t.N && col < cend) {
+          const T v = W[(size_t)r * ld + col];
+          W[(size_t)r * ld + col] = T{v.x + cr[a][s][i], v.y + ci[a][s][i]};
+        }
       }
 }
 
