@@ -246,9 +246,42 @@ def headline_leg(args, pxd, torch, spec, modes):
     return out
 
 
-def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False):
+def graph_rate(args, torch, ev, stream, inputs, n_max, eager, n_cand, label, mode):
+    """The same step captured once into a HIP graph (expand, order, evaluator,
+    FP64 re-solve, FoM, argmin; bound = the batch's largest active size) and
+    replayed: replays between HIP events on the capture's launch stream.
+    Every replay's S is checked against the eager step's."""
+    dev = torch.device("cuda:0")
+    P = eager["S"].shape[-1]
+    S_g = torch.empty((n_cand, eager["S"].shape[1], P, P, 2), dtype=torch.float64, device=dev)
+    F_g = torch.empty(n_cand, dtype=torch.float64, device=dev)
+    st_g = torch.empty(n_cand, dtype=torch.int32, device=dev)
+    am_g = torch.empty(1, dtype=torch.int32, device=dev)
+    g = ev.graph(*inputs, n_max, S_g, F_g, st_g, am_g)
+    dS = 0.0
+    g.launch(stream)  # warm-up replay
+    torch.cuda.synchronize()
+    dS = max(dS, float(np.abs(torch.view_as_complex(S_g.contiguous()).cpu().numpy() - eager["S"]).max()))
+    e0, e1 = _events(torch, stream)
+    e0.record(stream)
+    for _ in range(args.leg_steps):
+        g.launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.leg_steps
+    dS = max(dS, float(np.abs(torch.view_as_complex(S_g.contiguous()).cpu().numpy() - eager["S"]).max()))
+    am = int(am_g.cpu().numpy()[0])
+    g.close()
+    log(f"[{label} {mode}] graph replay: {n_cand / (ms / 1e3):.1f} evals/s ({ms:.0f} ms per replay), "
+        f"max |dS| vs eager {dS:.1e}")
+    return {"value": n_cand / (ms / 1e3), "ms_per_step": ms, "replays": args.leg_steps, "bound": n_max,
+            "max_dS_vs_eager": dS, "argmin_equal_eager": am == eager["am"]}
+
+
+def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False, graph=False):
     """Single-flip candidates of a workload at every frequency, device
-    buffers, one evaluator call per step."""
+    buffers, one evaluator call per step (and, with `graph`, the same step as
+    replays of a captured HIP graph)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     pb = pxd.Problem.from_spec(spec)
@@ -300,6 +333,9 @@ def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False):
                      "S": torch.view_as_complex(S_out.contiguous()).cpu().numpy()}
         log(f"[{label} {mode}] {out[mode]['value']:.1f} evals/s ({ms:.0f} ms per step, N {N.min()}-{N.max()}, "
             f"{s['fallbacks']} to FP64, {s['ir_iterations']} refinement steps)")
+        if graph and int(N.max()) <= 2048:
+            out[mode]["graph"] = graph_rate(args, torch, ev, stream, (t_base, t_off, t_cells), int(N.max()),
+                                            out[mode], n_cand, label, mode)
         ev.close()
         del S_out
         torch.cuda.empty_cache()
@@ -463,7 +499,7 @@ def main():
                                       "stress24")
     if "batched20" in legs:
         extra["batched20"] = batch_leg(args, pxd, torch, get_spec("batched20"), 800, ["fp64", "mixed32", "bf16x3"],
-                                       "batched20", tune=True)
+                                       "batched20", tune=True, graph=True)
     if "surrogate" in legs:
         extra["surrogate"] = surrogate_leg(args, pxd, get_spec("stress24"), torch)
     if "lowrank" in legs:

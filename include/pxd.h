@@ -150,7 +150,19 @@ typedef struct pxd_options {
                               per CU), 2 = 64 x 64 (three per CU); 0 = tuned, else 2 */
   double ws_gib;           /* tiled path: workspace cap in GiB (0 = 80 % of the free device memory,
                               at most 64 GiB); fixes how many items are factored together */
+  int32_t refine;          /* tiled path, mixed modes: PXD_REFINE_* */
 } pxd_options;
+
+/* Refinement of the tiled path's mixed modes.  Per item: each item's FP64
+ * residuals re-gather its rows of Z_A from the complex128 parent.  Lock step:
+ * the items of one frequency refine together, their residuals one product
+ * Z_f[U, U] X over the union U of the call's active sets (one pass over the
+ * parent rows per frequency and step); the stop test and the solves are the
+ * same, so the results agree up to the residuals' summation order.  Auto:
+ * lock step when |U| is at most 1.25 times the largest active size. */
+#define PXD_REFINE_AUTO 0
+#define PXD_REFINE_PER_ITEM 1
+#define PXD_REFINE_LOCKSTEP 2
 
 /* Dense LU of the evaluation (Eq. 2).  Persistent: one workgroup per item,
  * the whole factorisation and solve in one persistent launch over all items

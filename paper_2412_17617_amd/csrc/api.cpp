@@ -107,6 +107,11 @@ struct pxd_ctx {
   // tiled path: item order of the call (host copy) and its device copy
   std::vector<int> h_items, h_fb;
   DevBuf tl_items;
+  // tiled path, mixed modes, lock-step refinement: the union U of the call's
+  // active sets (marks, positions, list, size), the chunks' frequency-group
+  // tables and the groups' X and R blocks
+  DevBuf ir_mark, ir_upos, ir_ulist, ir_cnt, ir_tab, ir_xr;
+  std::vector<int> h_ir;
   // the no-allocation entry point's region of the static scratch array on this device
   char* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -250,7 +255,7 @@ int tiled_update(pxd_ctx* ctx, hipStream_t s, const pxd::TlParams& tp, const std
 // fb_list); else the FP64 augmented system (fallback: report FALLBACK).
 int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const std::vector<int>& list,
               const int* Nc, const int* Ilist, int* cnt, int* item_status, int* fb_list, double2* d_S, bool mixed,
-              bool fallback_mode) {
+              bool fallback_mode, int U = 0) {
   const int F = ctx->F, P = ctx->P;
   const int n = (int)list.size();
   if (n == 0) return PXD_OK;
@@ -286,7 +291,56 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
   tp.fb_count = cnt + 1;
   tp.fb_list = fb_list;
   HIPCHK(ctx, pxd::tl_prepare(tp, nmax_all));
-  for (int i0 = 0; i0 < n; i0 += bmax) {
+  // lock-step refinement (U > 0): the chunks' frequency groups.  Per chunk the
+  // table holds item_grp[B], item_col[B], then grp_f, grp_ncol and grp_active
+  // (zero) for its groups.
+  struct ChunkIr {
+    size_t off;
+    int n_grp, max_ncol;
+  };
+  std::vector<ChunkIr> cir;
+  int ldx = 0, n_grp_max = 0;
+  if (U > 0 && mixed && !fallback_mode) {
+    std::vector<int>& tab = ctx->h_ir;
+    tab.clear();
+    std::vector<int> gid(ctx->F, -1);
+    for (int i0 = 0; i0 < n; i0 += bmax) {
+      const int B = std::min(bmax, n - i0);
+      std::vector<int> gf, gn;
+      ChunkIr c{tab.size(), 0, 0};
+      tab.resize(tab.size() + 2 * (size_t)B);
+      for (int i = 0; i < B; ++i) {
+        const int f = list[i0 + i] % F;
+        if (gid[f] < 0) {
+          gid[f] = (int)gf.size();
+          gf.push_back(f);
+          gn.push_back(0);
+        }
+        const int g = gid[f];
+        tab[c.off + i] = g;
+        tab[c.off + B + i] = gn[g];
+        gn[g] += P;
+      }
+      for (int f : gf) gid[f] = -1;
+      c.n_grp = (int)gf.size();
+      for (int v : gn) c.max_ncol = std::max(c.max_ncol, v);
+      tab.insert(tab.end(), gf.begin(), gf.end());
+      tab.insert(tab.end(), gn.begin(), gn.end());
+      tab.insert(tab.end(), gf.size(), 0);
+      cir.push_back(c);
+      ldx = std::max(ldx, c.max_ncol);
+      n_grp_max = std::max(n_grp_max, c.n_grp);
+    }
+    const size_t xr = 2 * (size_t)n_grp_max * U * ldx * sizeof(double2);
+    if (xr > (size_t(4) << 30)) {
+      cir.clear();  // the groups' blocks would be too large: refine per item
+    } else {
+      HIPCHK(ctx, ctx->ir_tab.ensure(tab.size() * sizeof(int)));
+      HIPCHK(ctx, hipMemcpyAsync(ctx->ir_tab.p, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      HIPCHK(ctx, ctx->ir_xr.ensure(xr));
+    }
+  }
+  for (int i0 = 0, chunk = 0; i0 < n; i0 += bmax, ++chunk) {
     const int B = std::min(bmax, n - i0);
     int nmax = 0;
     for (int i = i0; i < i0 + B; ++i) nmax = std::max(nmax, ctx->hNc[list[i] / F]);
@@ -320,7 +374,31 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
         HIPCHK(ctx, pxd::tl_trsm(s, tp, K + kb, nmax));
       }
     }
-    HIPCHK(ctx, pxd::tl_finish(s, tp, nmax));
+    if (!cir.empty()) {
+      const ChunkIr& c = cir[chunk];
+      int* tab = ctx->ir_tab.as<int>() + c.off;
+      pxd::IrParams q{};
+      q.upos = ctx->ir_upos.as<int>();
+      q.ulist = ctx->ir_ulist.as<int>();
+      q.U = U;
+      q.ldx = ldx;
+      q.X = ctx->ir_xr.as<double2>();
+      q.R = q.X + (size_t)n_grp_max * U * ldx;
+      q.item_grp = tab;
+      q.item_col = tab + B;
+      q.grp_f = tab + 2 * B;
+      q.grp_ncol = tab + 2 * B + c.n_grp;
+      q.grp_active = tab + 2 * B + 2 * c.n_grp;
+      q.n_grp = c.n_grp;
+      HIPCHK(ctx, pxd::launch_zero_c128(s, q.X, (size_t)c.n_grp * U * ldx));
+      HIPCHK(ctx, pxd::tl_ir_init(s, tp, q, nmax));
+      for (int it = 0; it < std::max(1, ctx->opt.ir_max_iter); ++it) {
+        HIPCHK(ctx, pxd::tl_ir_residual(s, tp, q, c.max_ncol));
+        HIPCHK(ctx, pxd::tl_ir_step(s, tp, q, nmax));
+      }
+    } else {
+      HIPCHK(ctx, pxd::tl_finish(s, tp, nmax));
+    }
   }
   return PXD_OK;
 }
@@ -352,8 +430,21 @@ int evaluate_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, int C, const int* N
   HIPCHK(ctx, ctx->tl_items.ensure(sizeof(int) * (size_t)items));
   HIPCHK(ctx, hipMemcpyAsync(ctx->tl_items.p, order.data(), sizeof(int) * (size_t)items, hipMemcpyHostToDevice, s));
   HIPCHK(ctx, pxd::launch_fill_int(s, cnt, 8, 0));
+  int U = 0;  // lock-step refinement: the union of the call's active sets
+  if (mixed && ctx->opt.refine != PXD_REFINE_PER_ITEM) {
+    const int M = ctx->M;
+    HIPCHK(ctx, ctx->ir_mark.ensure(sizeof(int) * (size_t)M));
+    HIPCHK(ctx, ctx->ir_upos.ensure(sizeof(int) * (size_t)M));
+    HIPCHK(ctx, ctx->ir_ulist.ensure(sizeof(int) * (size_t)M));
+    HIPCHK(ctx, ctx->ir_cnt.ensure(sizeof(int)));
+    HIPCHK(ctx, pxd::launch_union(s, Nc, Ilist, C, M, ctx->ir_mark.as<int>(), ctx->ir_upos.as<int>(),
+                                  ctx->ir_ulist.as<int>(), ctx->ir_cnt.as<int>()));
+    HIPCHK(ctx, hipMemcpyAsync(&U, ctx->ir_cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (ctx->opt.refine == PXD_REFINE_AUTO && (double)U > 1.25 * nmax) U = 0;
+  }
   int rc = run_tiled(ctx, b, s, ctx->tl_items.as<int>(), order, Nc, Ilist, cnt, item_status, fb_list, d_S, mixed,
-                     false);
+                     false, U);
   if (rc) return rc;
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
   if (mixed) {  // FP64 re-solve of the items refinement could not settle
@@ -785,6 +876,10 @@ int pxd_create(const pxd_options* opt, pxd_ctx** out) {
   if (ctx->opt.precision < PXD_PREC_FP64 || ctx->opt.precision > PXD_PREC_MIXED_BF16X3) {
     delete ctx;
     return pxd::set_thread_error(PXD_EINVAL, "unknown precision mode");
+  }
+  if (ctx->opt.refine < PXD_REFINE_AUTO || ctx->opt.refine > PXD_REFINE_LOCKSTEP) {
+    delete ctx;
+    return pxd::set_thread_error(PXD_EINVAL, "unknown refinement mode");
   }
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);

@@ -149,8 +149,9 @@ constexpr int kTlKbMax = 128;  // widest block column of the tiled LU
 
 // Per-item slot of the tiled path: the item's matrix (row-major, ld), its
 // pivots, an auxiliary block (flags, the current block column's touched rows
-// and their sources), the inverse of the block column's unit-lower diagonal
-// block (kTlKbMax x kTlKbMax) and, in the mixed modes, the FP64 solution.
+// and their sources, the lock-step refinement's state), the inverse of the
+// block column's unit-lower diagonal block (kTlKbMax x kTlKbMax) and, in the
+// mixed modes, the FP64 solution.
 struct TlLayout {
   int ld;
   size_t piv_off, aux_off, li_off, x_off, bytes;
@@ -164,7 +165,7 @@ __host__ __device__ inline TlLayout tl_layout(int nmax, int P, bool mixed) {
   s.piv_off = o;
   o += up((size_t)nmax * 4, 256);
   s.aux_off = o;
-  o += up((size_t)(4 + 4 * kTlKbMax) * 4, 256);
+  o += up((size_t)(4 + 4 * kTlKbMax) * 4 + 16, 256);  // + the refinement state
   s.li_off = o;
   o += up((size_t)kTlKbMax * kTlKbMax * es, 256);
   s.x_off = o;
@@ -212,6 +213,37 @@ hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax, int cb, 
 hipError_t tl_finish(hipStream_t s, const TlParams& p, int nmax);
 hipError_t tl_prepare(const TlParams& p, int nmax);  // kernel attributes (outside capture)
 int tl_max_active();                                 // largest active size the tiled path takes
+
+// Lock-step refinement of a mixed-mode chunk.  U is the union of the batch's
+// active sets (ascending parent indices).  The chunk's items are grouped by
+// frequency; each group keeps the solutions of its items as columns of one
+// U-row block X (a candidate's rows outside its active set stay zero), so
+// one product R = Z_f[U, U] X per group and step gives every residual of the
+// group (r = V - (Z_A + port loads) x on the item's rows of R).
+struct IrParams {
+  const int* upos;      // M: position of each parent function in U, -1 outside U
+  const int* ulist;     // U entries
+  int U;
+  int ldx;              // columns of one group's X and R blocks
+  double2* X;           // n_grp x U x ldx
+  double2* R;           // n_grp x U x ldx
+  const int* grp_f;     // per group: frequency
+  const int* grp_ncol;  // per group: columns in use (items x P)
+  int* grp_active;      // per group: items still refining
+  const int* item_grp;  // per chunk item: group
+  const int* item_col;  // per chunk item: first column of its solution in the group
+  int n_grp;
+};
+// After the factorisation of a chunk: x0 = (LU)^-1 V per item, into its slot and X.
+hipError_t tl_ir_init(hipStream_t s, const TlParams& p, const IrParams& q, int nmax);
+// R = Z_f[U, U] X for every group that still has an item refining.
+hipError_t tl_ir_residual(hipStream_t s, const TlParams& p, const IrParams& q, int max_ncol);
+// One refinement step of every item still refining (stop test, solve, update).
+hipError_t tl_ir_step(hipStream_t s, const TlParams& p, const IrParams& q, int nmax);
+// U: mark (M ints, zeroed here), upos (M), ulist (M), count[0] = |U|.
+hipError_t launch_union(hipStream_t s, const int* Nc, const int* Ilist, int C, int M, int* mark, int* upos,
+                        int* ulist, int* count);
+hipError_t launch_zero_c128(hipStream_t s, double2* p, size_t n);
 
 // Rows of the register-resident sub-panel per thread for a given active size.
 __host__ __device__ inline int rows_per_thread(int nmax) { return (nmax + 255) / 256; }

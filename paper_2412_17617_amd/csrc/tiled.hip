@@ -49,9 +49,12 @@ __device__ __forceinline__ TlItem tl_item(const TlParams& p, int b) {
 __device__ __forceinline__ int* tl_aux(const TlParams& p, int b) {
   return reinterpret_cast<int*>(p.ws + (size_t)b * p.slot_bytes + p.lay.aux_off);
 }
-// aux: [0] zero-pivot flag, [1] touched-row count, tr[2 kTlKbMax], src[2 kTlKbMax]
+// aux: [0] zero-pivot flag, [1] touched-row count, tr[2 kTlKbMax], src[2 kTlKbMax],
+// then the lock-step refinement's state: still refining, steps taken, and (as
+// a double) the largest change of the last step
 constexpr int kAuxTr = 4;
 constexpr int kAuxSrc = 4 + 2 * kTlKbMax;
+constexpr int kAuxIr = 4 + 4 * kTlKbMax;
 
 // ------------------------------------------------------------------ gather
 
@@ -603,6 +606,281 @@ __global__ __launch_bounds__(256) void k_tl_finish_mixed(TlParams p, int nmax) {
               p.fb_count, p.fb_list);
 }
 
+// ------------------------------------------------------------------ lock-step refinement
+//
+// The mixed modes' refinement of a chunk, all items a step at a time.  The
+// FP64 residual r = V - (Z_A + loads) x of every item of one frequency comes
+// from one product R = Z_f[U, U] X over the union U of the batch's active
+// sets: the parent rows are read once per group and step instead of once
+// per item and step.  The stop test, the complex64 solve and the update are
+// those of the per-item form (refine_verdict, lu_solve_c64).
+
+__device__ __forceinline__ double* ir_mprev(int* aux) { return reinterpret_cast<double*>(aux + kAuxIr + 2); }
+
+// x0 = (LU)^-1 V for one item, into its slot and into its group's X block.
+__global__ __launch_bounds__(256) void k_ir_init(TlParams p, IrParams q, int nmax) {
+  extern __shared__ char dyn[];
+  float2* bvec = reinterpret_cast<float2*>(dyn + ((size_t)nmax * 4 + 15) / 16 * 16);
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const TlItem t = tl_item(p, b);
+  char* slot = p.ws + (size_t)b * p.slot_bytes;
+  const float2* W = reinterpret_cast<const float2*>(slot);
+  const int* piv = reinterpret_cast<const int*>(slot + p.lay.piv_off);
+  int* aux = reinterpret_cast<int*>(slot + p.lay.aux_off);
+  double2* x = reinterpret_cast<double2*>(slot + p.lay.x_off);
+  const int N = t.N, P = p.P;
+  for (int e = tid; e < N * P; e += kThreads) {
+    const int i = e / P, jr = e - i * P;
+    bvec[e] = float2{(i == N - P + jr) ? (float)p.port_len[jr] : 0.0f, 0.0f};
+  }
+  __syncthreads();
+  lu_solve_c64(W, p.lay.ld, N, piv, bvec, P, p.kb);
+  const int g = q.item_grp[b], col = q.item_col[b];
+  double2* X = q.X + (size_t)g * q.U * q.ldx;
+  const int* I = p.Ilist + (size_t)t.c * p.M;
+  for (int e = tid; e < N * P; e += kThreads) {
+    const int i = e / P, jr = e - i * P;
+    const double2 v = double2{(double)bvec[e].x, (double)bvec[e].y};
+    x[e] = v;
+    X[(size_t)q.upos[I[i]] * q.ldx + col + jr] = v;
+  }
+  if (tid == 0) {
+    aux[kAuxIr] = 1;
+    aux[kAuxIr + 1] = 0;
+    *ir_mprev(aux) = 0.0;
+    atomicAdd(q.grp_active + g, 1);
+  }
+}
+
+// R = Z_f[U, U] X for one 64 x 64 tile of one group.  Four waves, each 16 rows
+// by 64 columns (four 16 x 16 FP64 MFMA tiles, real and imaginary
+// accumulators); Z rows and columns are gathered from the parent through U,
+// eight k per LDS stage.
+constexpr int kIrTM = 64, kIrTN = 64, kIrKC = 8;
+__global__ __launch_bounds__(256) void k_ir_residual(TlParams p, IrParams q) {
+  using MF = Mfma<double>;
+  using acc_t = typename MF::acc_t;
+  constexpr int TM = kIrTM, TN = kIrTN, KC = kIrKC, SA = KC + 1, SBS = TN + 2;
+  constexpr int NA = TM * KC / kThreads, NBV = KC * TN / kThreads;
+  static_assert(TM * KC % kThreads == 0 && KC * TN % kThreads == 0 && TM == 16 * kWaves, "tile split");
+  __shared__ double Ar[TM * SA], Ai[TM * SA], Br[KC * SBS], Bi[KC * SBS];
+  const int g = blockIdx.z;
+  if (q.grp_active[g] == 0) return;
+  const int ncol = q.grp_ncol[g];
+  const int r0 = blockIdx.x * TM, c0 = blockIdx.y * TN;
+  if (r0 >= q.U || c0 >= ncol) return;
+  const double2* Zf = p.Z128 + (size_t)q.grp_f[g] * p.M * p.M;
+  const double2* X = q.X + (size_t)g * q.U * q.ldx;
+  double2* R = q.R + (size_t)g * q.U * q.ldx;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  acc_t cr[4], ci[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cr[s][i] = ci[s][i] = 0.0;
+  for (int k0 = 0; k0 < q.U; k0 += KC) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
+      const int r = r0 + row, k = k0 + kk;
+      const double2 v = (r < q.U && k < q.U) ? Zf[(size_t)q.ulist[r] * p.M + q.ulist[k]] : double2{0.0, 0.0};
+      Ar[row * SA + kk] = v.x;
+      Ai[row * SA + kk] = v.y;
+    }
+#pragma unroll
+    for (int i = 0; i < NBV; ++i) {
+      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
+      const int k = k0 + kr, c = c0 + col;
+      const double2 v = (k < q.U && c < ncol) ? X[(size_t)k * q.ldx + c] : double2{0.0, 0.0};
+      Br[kr * SBS + col] = v.x;
+      Bi[kr * SBS + col] = v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < KC / 4; ++kq) {
+      const int row = wid * 16 + l16;
+      const double ar = Ar[row * SA + 4 * kq + lk], ai = Ai[row * SA + 4 * kq + lk], nai = -ai;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double br = Br[(4 * kq + lk) * SBS + 16 * s + l16], bi = Bi[(4 * kq + lk) * SBS + 16 * s + l16];
+        cr[s] = MF::run(ar, br, cr[s]);
+        ci[s] = MF::run(ar, bi, ci[s]);
+        cr[s] = MF::run(nai, bi, cr[s]);
+        ci[s] = MF::run(ai, br, ci[s]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + wid * 16 + MF::row(lane, i), c = c0 + 16 * s + l16;
+      if (r < q.U && c < ncol) R[(size_t)r * q.ldx + c] = double2{cr[s][i], ci[s][i]};
+    }
+}
+
+// One refinement step of one item still refining: its residual from R, the
+// port corrections and the stop test; converged: S and the status; given up
+// (or the step budget spent): handed to the FP64 path; else the complex64
+// solve of the correction, x += d, and x back into X.
+__global__ __launch_bounds__(256) void k_ir_step(TlParams p, IrParams q, int nmax) {
+  extern __shared__ char dyn[];
+  int* sP = reinterpret_cast<int*>(dyn);  // U positions of the item's rows
+  float2* bvec = reinterpret_cast<float2*>(dyn + ((size_t)nmax * 4 + 15) / 16 * 16);
+  __shared__ int s_v;
+  __shared__ double s_ds[16], s_sabs[16];
+  __shared__ double2 s_delta[16], s_part[kWaves * 16];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  char* slot = p.ws + (size_t)b * p.slot_bytes;
+  int* aux = reinterpret_cast<int*>(slot + p.lay.aux_off);
+  if (aux[kAuxIr] == 0) return;  // the same word for every thread
+  const TlItem t = tl_item(p, b);
+  const float2* W = reinterpret_cast<const float2*>(slot);
+  const int* piv = reinterpret_cast<const int*>(slot + p.lay.piv_off);
+  double2* x = reinterpret_cast<double2*>(slot + p.lay.x_off);
+  const int N = t.N, P = p.P;
+  const int g = q.item_grp[b], col = q.item_col[b];
+  const double2* R = q.R + (size_t)g * q.U * q.ldx;
+  double2* X = q.X + (size_t)g * q.U * q.ldx;
+  const int* I = p.Ilist + (size_t)t.c * p.M;
+  for (int i = tid; i < N; i += kThreads) sP[i] = q.upos[I[i]];
+  __syncthreads();
+  for (int e = tid; e < N * P; e += kThreads) {
+    const int i = e / P, jr = e - i * P;
+    const double2 zx = R[(size_t)sP[i] * q.ldx + col + jr];
+    double2 r = double2{-zx.x, -zx.y};
+    const int pi = i - (N - P);  // port index of this row, if it is a port row
+    if (pi >= 0) {
+      const double load = p.z0 * p.port_len[pi] * p.port_len[pi];
+      const double2 xv = x[e];
+      r.x -= load * xv.x;
+      r.y -= load * xv.y;
+      if (pi == jr) r.x += p.port_len[pi];  // V: 1 V source EMF in the gap of port jr
+    }
+    bvec[e] = float2{(float)r.x, (float)r.y};
+  }
+  __syncthreads();
+  const int iters = aux[kAuxIr + 1] + 1;
+  port_corrections(x, bvec, N, P, p.port_len, s_delta, s_part);
+  if (tid == 0) {
+    double m = 0.0;
+    for (int qq = 0; qq < P * P; ++qq) {
+      const int i = qq / P, j = qq - i * P;
+      const double gg = 2.0 * p.z0 * p.port_len[i];
+      const double ds = gg * sqrt(s_delta[qq].x * s_delta[qq].x + s_delta[qq].y * s_delta[qq].y);
+      m = (ds > m || ds != ds) ? ds : m;
+      const double2 xv = x[(size_t)(N - P + i) * P + j];
+      const double sr = (i == j ? 1.0 : 0.0) - gg * (xv.x + s_delta[qq].x), si = -gg * (xv.y + s_delta[qq].y);
+      s_sabs[qq] = sqrt(sr * sr + si * si);
+    }
+    double target = 1e300;
+    for (int qq = 0; qq < P * P; ++qq) target = fmin(target, p.ir_tol * s_sabs[qq] + kIrAbsFloor);
+    int v = refine_verdict(iters, p.ir_max, m, *ir_mprev(aux), target);
+    if (v == 0 && iters >= p.ir_max) v = 2;  // no step left
+    s_v = v;
+  }
+  __syncthreads();
+  const int v = s_v;
+  const size_t item = (size_t)t.c * p.F + t.f;
+  if (v == 1) {  // converged: the port corrections finish the step
+    if (tid < P * P) {
+      double2* xv = x + (size_t)(N - P + tid / P) * P + tid % P;
+      xv->x += s_delta[tid].x;
+      xv->y += s_delta[tid].y;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      bool finite = true;
+      double2* Sout = p.S + item * P * P;
+      for (int i = 0; i < P; ++i)
+        for (int j = 0; j < P; ++j) {
+          const double2 xv = x[(size_t)(N - P + i) * P + j];
+          const double2 sv = double2{(i == j ? 1.0 : 0.0) - 2.0 * p.z0 * p.port_len[i] * xv.x,
+                                     -2.0 * p.z0 * p.port_len[i] * xv.y};
+          finite = finite && isfinite(sv.x) && isfinite(sv.y);
+          Sout[i * P + j] = sv;
+        }
+      int st = PXD_STATUS_OK;
+      if (!finite) st = PXD_STATUS_NONFINITE;
+      else if (aux[0]) st = PXD_STATUS_SINGULAR;
+      p.status[item] = st;
+      aux[kAuxIr] = 0;
+      atomicSub(q.grp_active + g, 1);
+      atomicAdd(p.ir_iters, iters);
+    }
+    return;
+  }
+  if (v == 2) {  // the FP64 path takes the item
+    if (tid == 0) {
+      p.status[item] = PXD_STATUS_FALLBACK;
+      p.fb_list[atomicAdd(p.fb_count, 1)] = (int)item;
+      aux[kAuxIr] = 0;
+      atomicSub(q.grp_active + g, 1);
+      atomicAdd(p.ir_iters, iters);
+    }
+    return;
+  }
+  lu_solve_c64(W, p.lay.ld, N, piv, bvec, P, p.kb);
+  for (int e = tid; e < N * P; e += kThreads) {
+    const int i = e / P, jr = e - i * P;
+    const double2 d = double2{(double)bvec[e].x, (double)bvec[e].y};
+    double2 xv = x[e];
+    xv.x += d.x;
+    xv.y += d.y;
+    x[e] = xv;
+    X[(size_t)sP[i] * q.ldx + col + jr] = xv;
+    if (i >= N - P) s_ds[(i - (N - P)) * P + jr] = 2.0 * p.z0 * p.port_len[i - (N - P)] * sqrt(d.x * d.x + d.y * d.y);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int qq = 0; qq < P * P; ++qq) m = (s_ds[qq] > m || s_ds[qq] != s_ds[qq]) ? s_ds[qq] : m;
+    *ir_mprev(aux) = m;
+    aux[kAuxIr + 1] = iters;
+  }
+}
+
+// Union of the batch's active sets: marks, then one workgroup's prefix sum.
+__global__ void k_union_mark(const int* __restrict__ Nc, const int* __restrict__ Ilist, int M, int* mark) {
+  const int c = blockIdx.x;
+  const int* I = Ilist + (size_t)c * M;
+  for (int i = threadIdx.x; i < Nc[c]; i += blockDim.x) mark[I[i]] = 1;
+}
+
+__global__ __launch_bounds__(1024) void k_union_scan(const int* __restrict__ mark, int M, int* upos, int* ulist,
+                                                     int* count) {
+  __shared__ int part[1024];
+  const int tid = threadIdx.x, per = (M + 1023) / 1024;
+  const int lo = min(M, tid * per), hi = min(M, lo + per);
+  int n = 0;
+  for (int m = lo; m < hi; ++m) n += mark[m] ? 1 : 0;
+  part[tid] = n;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+    const int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int pos = part[tid] - n;
+  for (int m = lo; m < hi; ++m) {
+    if (mark[m]) {
+      upos[m] = pos;
+      ulist[pos++] = m;
+    } else {
+      upos[m] = -1;
+    }
+  }
+  if (tid == 1023) count[0] = part[1023];
+}
+
+__global__ void k_zero_c128(double2* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = double2{0.0, 0.0};
+}
+
 template <typename R, int Q>
 constexpr int tl_sb() {
   return sizeof(R) == 8 ? (16 / Q > 0 ? 16 / Q : 1) : (32 / Q > 0 ? 32 / Q : 1);
@@ -700,8 +978,46 @@ hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax, int cb, 
 
 hipError_t tl_prepare(const TlParams& p, int nmax) {
   if (!p.mixed) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tl_finish_mixed),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)eval_mixed_lds(nmax, p.P));
+  const int lds = (int)eval_mixed_lds(nmax, p.P);
+  for (const void* k : {reinterpret_cast<const void*>(&k_tl_finish_mixed), reinterpret_cast<const void*>(&k_ir_init),
+                        reinterpret_cast<const void*>(&k_ir_step)}) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t tl_ir_init(hipStream_t s, const TlParams& p, const IrParams& q, int nmax) {
+  hipLaunchKernelGGL(k_ir_init, dim3(p.B), dim3(kThreads), eval_mixed_lds(nmax, p.P), s, p, q, nmax);
+  return hipGetLastError();
+}
+
+hipError_t tl_ir_residual(hipStream_t s, const TlParams& p, const IrParams& q, int max_ncol) {
+  if (q.U <= 0 || max_ncol <= 0 || q.n_grp <= 0) return hipSuccess;
+  const dim3 g((q.U + kIrTM - 1) / kIrTM, (max_ncol + kIrTN - 1) / kIrTN, q.n_grp);
+  hipLaunchKernelGGL(k_ir_residual, g, dim3(kThreads), 0, s, p, q);
+  return hipGetLastError();
+}
+
+hipError_t tl_ir_step(hipStream_t s, const TlParams& p, const IrParams& q, int nmax) {
+  hipLaunchKernelGGL(k_ir_step, dim3(p.B), dim3(kThreads), eval_mixed_lds(nmax, p.P), s, p, q, nmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_union(hipStream_t s, const int* Nc, const int* Ilist, int C, int M, int* mark, int* upos,
+                        int* ulist, int* count) {
+  hipError_t e = launch_fill_int(s, mark, M, 0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_union_mark, dim3(C), dim3(256), 0, s, Nc, Ilist, M, mark);
+  hipLaunchKernelGGL(k_union_scan, dim3(1), dim3(1024), 0, s, mark, M, upos, ulist, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_c128(hipStream_t s, double2* p, size_t n) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_zero_c128, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
 }
 
 hipError_t tl_finish(hipStream_t s, const TlParams& p, int nmax) {

@@ -21,6 +21,7 @@ KIND_ALWAYS, KIND_INNER, KIND_INTER, KIND_PIXPORT, KIND_VIA = 0, 1, 2, 3, 4
 STATUS_OK, STATUS_FALLBACK, STATUS_NONFINITE, STATUS_SINGULAR, STATUS_SIZE = 0, 1, -1, -2, -3
 SCHED_AUTO, SCHED_FREQ_MAJOR, SCHED_SIZE_MAJOR = 0, 1, 2
 PATH_AUTO, PATH_PERSISTENT, PATH_TILED = 0, 1, 2
+REFINE_AUTO, REFINE_PER_ITEM, REFINE_LOCKSTEP = 0, 1, 2
 FOM_PAPER, FOM_REJ, FOM_ISO = 0, 1, 2
 SIDES = {"right": 0, "top": 1, "left": 2, "bottom": 3}
 
@@ -45,6 +46,7 @@ class Options(C.Structure):
         ("device", C.c_int32), ("precision", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
         ("wg_per_cu", C.c_int32), ("half_subpanel", C.c_int32), ("schedule", C.c_int32),
         ("lu_path", C.c_int32), ("tile_kb", C.c_int32), ("tile_shape", C.c_int32), ("ws_gib", C.c_double),
+        ("refine", C.c_int32),
     ]
 
 
@@ -219,9 +221,9 @@ class Evaluator:
     """GPU evaluator context (one per device and host thread)."""
 
     def __init__(self, device=0, precision=PREC_FP64, ir_max_iter=10, ir_tol=1e-7, wg_per_cu=0, half_subpanel=0,
-                 schedule=SCHED_AUTO, lu_path=0, tile_kb=0, tile_shape=0, ws_gib=0.0):
+                 schedule=SCHED_AUTO, lu_path=0, tile_kb=0, tile_shape=0, ws_gib=0.0, refine=0):
         o = Options(device, precision, ir_max_iter, ir_tol, wg_per_cu, half_subpanel, schedule, lu_path, tile_kb,
-                    tile_shape, ws_gib)
+                    tile_shape, ws_gib, refine)
         h_ = _VP()
         _check(lib().pxd_create(C.byref(o), C.byref(h_)))
         self._h = h_

@@ -205,3 +205,50 @@ def test_plain_half_modes_above_2048_are_refused():
             ev.evaluate_flips(spec.base_map(), off, cells)
         assert e.value.code == pxd.ESHAPE
         ev.close()
+
+
+@pytest.mark.parametrize("prec", [pxd.PREC_MIXED32, pxd.PREC_MIXED_BF16X3])
+@pytest.mark.parametrize("maps", [False, True])
+def test_lockstep_refinement_matches_per_item(prec, maps):
+    """The lock-step refinement (the residuals of one frequency's items as
+    one product over the union of the active sets) against the per-item form
+    and the oracle.  Single flips of one map (union ~ one active set), or
+    whole maps of densities 0.3-0.9 as flips of the empty map (union ~ the
+    parent, candidates of very different sizes in one frequency group);
+    five frequencies."""
+    spec = get_spec("small6x3")
+    st, Z, freqs = oracle_parent(spec)
+    if maps:
+        rng = np.random.default_rng(5)
+        on = [np.nonzero(rng.random(spec.n_cells) < d)[0] for d in np.linspace(0.3, 0.9, 7)]
+        base = np.zeros(spec.n_cells, np.uint8)
+        off = np.zeros(len(on) + 1, np.int32)
+        off[1:] = np.cumsum([len(c) for c in on])
+        cells = np.concatenate(on).astype(np.int32)
+    else:
+        base = spec.base_map()
+        off, cells = spec.flips()
+        off, cells = off[:25], cells[:off[24]]
+    print(f"small6x3 precision {prec} {'whole maps' if maps else 'single flips'}: {len(off) - 1} candidates",
+          flush=True)
+    S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
+    out = {}
+    for refine in (pxd.REFINE_PER_ITEM, pxd.REFINE_LOCKSTEP):
+        ev, _ = make_evaluator(spec, Z, freqs, precision=prec, lu_path=pxd.PATH_TILED, refine=refine)
+        S, F, status, am = ev.evaluate_flips(base, off, cells)
+        stats = ev.stats()
+        ev.close()
+        out[refine] = (S, F, status, am, stats)
+        print(f"  refine {refine}: N {stats['min_active']}-{stats['max_active']}, max |dS| vs oracle "
+              f"{np.abs(S - S_o).max():.2e}, fallbacks {stats['fallbacks']}, steps {stats['ir_iterations']}",
+              flush=True)
+        assert np.all((status == pxd.STATUS_OK) | (status == pxd.STATUS_FALLBACK))
+        assert np.abs(S - S_o).max() <= 1e-4
+        _check_fom(F, F_o, am)
+        if prec == pxd.PREC_MIXED32:
+            assert stats["fallbacks"] == 0
+    S1, S2 = out[pxd.REFINE_PER_ITEM][0], out[pxd.REFINE_LOCKSTEP][0]
+    assert np.abs(S1 - S2).max() <= 1e-6
+    # the same stop test on residuals that differ only in summation order
+    assert abs(out[pxd.REFINE_PER_ITEM][4]["ir_iterations"] - out[pxd.REFINE_LOCKSTEP][4]["ir_iterations"]) <= \
+        0.05 * out[pxd.REFINE_PER_ITEM][4]["ir_iterations"] + 2
