@@ -334,8 +334,12 @@ def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False, graph=Fa
         log(f"[{label} {mode}] {out[mode]['value']:.1f} evals/s ({ms:.0f} ms per step, N {N.min()}-{N.max()}, "
             f"{s['fallbacks']} to FP64, {s['ir_iterations']} refinement steps)")
         if graph and int(N.max()) <= 2048:
-            out[mode]["graph"] = graph_rate(args, torch, ev, stream, (t_base, t_off, t_cells), int(N.max()),
-                                            out[mode], n_cand, label, mode)
+            try:
+                out[mode]["graph"] = graph_rate(args, torch, ev, stream, (t_base, t_off, t_cells), int(N.max()),
+                                                out[mode], n_cand, label, mode)
+            except pxd.PxdError as e:
+                log(f"[{label} {mode}] graph not timed: {e}")
+                out[mode]["graph"] = {"error": str(e)}
         ev.close()
         del S_out
         torch.cuda.empty_cache()

@@ -146,8 +146,10 @@ typedef struct pxd_options {
   int32_t schedule;        /* PXD_SCHED_* */
   int32_t lu_path;         /* PXD_PATH_*: which dense LU solves the items */
   int32_t tile_kb;         /* tiled path: block-column width 64 or 128 (0 = tuned, else 128) */
-  int32_t tile_shape;      /* tiled path: output tile of the trailing update, 1 = 128 x 64 (two workgroups
-                              per CU), 2 = 64 x 64 (three per CU); 0 = tuned, else 2 */
+  int32_t tile_shape;      /* tiled path: output tile of the trailing update, 1 = 128 x 64 (four waves, two
+                              workgroups per CU), 2 = 64 x 64 (four waves, three per CU), 3 = 128 x 64 (eight
+                              waves, two per CU), 4 = 128 x 128 (eight waves, one per CU); 3 and 4 are FP64 and
+                              FP32 updates only (the split-BF16 update takes 1 for them); 0 = tuned, else 2 */
   double ws_gib;           /* tiled path: workspace cap in GiB (0 = 80 % of the free device memory,
                               at most 64 GiB); fixes how many items are factored together */
   int32_t refine;          /* tiled path, mixed modes: PXD_REFINE_* */

@@ -179,13 +179,16 @@ struct Arena {
 // Whether the batch's dense solves go to the tiled LU: the option, else the
 // tuned choice for the size class, else tiled only above the persistent
 // kernels' 2,048 limit.
-bool use_tiled(const pxd_ctx* ctx, int nmax) {
+// may_tile: false where the tiled path cannot run (graphs, the no-allocation
+// entry point): a tuned preference for it then yields the persistent path;
+// only what needs the tiled path selects it there (and is refused).
+bool use_tiled(const pxd_ctx* ctx, int nmax, bool may_tile = true) {
   const int prec = ctx->opt.precision;
   if (prec == PXD_PREC_MIXED_BF16X3) return true;  // split-BF16 updates exist on the tiled path only
   if (prec == PXD_PREC_MIXED_BF16 || prec == PXD_PREC_MIXED_F16) return false;  // plain ones on the persistent
   const bool no_c64 = prec != PXD_PREC_FP64 && !ctx->Z64.p;
   if (ctx->opt.lu_path == PXD_PATH_TILED || nmax > 2048 || no_c64) return true;
-  if (ctx->opt.lu_path == PXD_PATH_PERSISTENT) return false;
+  if (ctx->opt.lu_path == PXD_PATH_PERSISTENT || !may_tile) return false;
   if (ctx->forced) return ctx->forced->tiled;
   const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(pxd::rows_per_thread(nmax))];
   return t.valid && t.tiled;
@@ -199,7 +202,7 @@ int tile_kb(const pxd_ctx* ctx, int nmax) {
 }
 
 int tile_shape(const pxd_ctx* ctx, int nmax) {
-  if (ctx->opt.tile_shape == 1 || ctx->opt.tile_shape == 2) return ctx->opt.tile_shape;
+  if (ctx->opt.tile_shape >= 1 && ctx->opt.tile_shape <= 4) return ctx->opt.tile_shape;
   if (ctx->forced && ctx->forced->tile_shape) return ctx->forced->tile_shape;
   const Tuning& t = ctx->tuned[ctx->opt.precision][size_class(pxd::rows_per_thread(nmax))];
   return (t.valid && t.tile_shape) ? t.tile_shape : 2;
@@ -537,7 +540,7 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
     }
     if (nmin < P) return ctx->fail(PXD_ESHAPE, "candidate with fewer active functions than ports");
   }
-  const bool tiled = use_tiled(ctx, nmax);
+  const bool tiled = use_tiled(ctx, nmax, !(arena || nmax_bound > 0));
   if (tiled) {
     if (arena || nmax_bound > 0)
       return ctx->fail(PXD_ESHAPE, "the tiled LU (active sizes above 2,048) is not available in graphs or the "
@@ -1191,7 +1194,7 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
   const int sched_lo = sched_fixed ? ctx->opt.schedule : PXD_SCHED_FREQ_MAJOR;
   const int sched_hi = sched_fixed ? ctx->opt.schedule : PXD_SCHED_SIZE_MAJOR;
   const bool kb_fixed = ctx->opt.tile_kb == 64 || ctx->opt.tile_kb == 128;
-  const bool shape_fixed = ctx->opt.tile_shape == 1 || ctx->opt.tile_shape == 2;
+  const bool shape_fixed = ctx->opt.tile_shape >= 1 && ctx->opt.tile_shape <= 4;
   // the batch's largest active size decides which paths can take it
   int nmax_batch = 0;
   {
@@ -1220,8 +1223,9 @@ int pxd_autotune(pxd_ctx* ctx, const uint8_t* base_map, int32_t n_cand, const in
   if (try_tiled)
     for (int kb : {64, 128}) {
       if (kb_fixed && kb != ctx->opt.tile_kb) continue;
-      for (int shape : {1, 2}) {
+      for (int shape : {1, 2, 3, 4}) {
         if (shape_fixed && shape != ctx->opt.tile_shape) continue;
+        if (shape > 2 && prec == PXD_PREC_MIXED_BF16X3) continue;  // the split-BF16 update has two shapes
         for (int sched = sched_lo; sched <= sched_hi; ++sched) {
           Tuning t;
           t.wg_per_cu = 0, t.schedule = sched, t.tiled = true, t.tile_kb = kb, t.tile_shape = shape, t.valid = true;

@@ -189,7 +189,8 @@ struct TlParams {
   TlLayout lay;
   int mixed;            // 0: FP64 augmented [Z_A | V] (eliminate N - P columns), 1: complex64 N x N
   int kb;               // block-column width (64 or 128)
-  int shape;            // output tile of the trailing update: 0 = 128 x 64, 1 = 64 x 64
+  int shape;            // output tile of the trailing update: 0 = 128 x 64, 1 = 64 x 64 (four waves),
+                        // 2 = 128 x 64, 3 = 128 x 128 (eight waves; FP32 and FP64 only)
   int half;             // mixed: operands of the trailing updates (PXD_HALF_*)
   double2* S;           // C x F x P x P
   int* status;          // C x F

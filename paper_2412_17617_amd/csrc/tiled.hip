@@ -301,9 +301,8 @@ __global__ __launch_bounds__(256) void k_tl_trsm(TlParams p, int K) {
 // ------------------------------------------------------------------ trailing update
 
 // A22 -= L21 U12 for one TM x TN output tile of one item, rows [Kend, N),
-// columns [Kend, ncols).  Four waves in a 2 x 2 grid, each owning a
-// (TM/2) x (TN/2) block of 16 x 16 MFMA tiles (real and imaginary
-// accumulators).  L21 and U12 are staged in LDS as planar real/imaginary
+// columns [Kend, ncols).  WGM x WGN waves, each owning a (TM/WGM) x (TN/WGN)
+// block of 16 x 16 MFMA tiles (real and imaginary accumulators).  L21 and U12 are staged in LDS as planar real/imaginary
 // tiles, KC columns of L21 (rows as stored, row stride KC + pad) and KC rows
 // of U12 (row stride TN + 16) at a time; the strides make the fragment reads
 // of a wave hit distinct banks.  The next stage's tiles are fetched into
@@ -312,16 +311,18 @@ __global__ __launch_bounds__(256) void k_tl_trsm(TlParams p, int K) {
 // wave's tiles, so no MFMA waits on the one before it.  The block id is
 // remapped so that the tiles of one item run on one XCD (workgroups are
 // dealt to the XCDs in turn).
-template <typename R, int TM, int TN, int KC, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_tl_update(TlParams p, int K, int tiles_m, int tiles_n, int cb, int ce) {
+template <typename R, int TM, int TN, int KC, int OCC, int WGM = 2, int WGN = 2>
+__global__ __launch_bounds__(64 * WGM * WGN, OCC) void k_tl_update(TlParams p, int K, int tiles_m, int tiles_n, int cb,
+                                                                   int ce) {
   using T = typename Cx<R>::T;
   using MF = Mfma<R>;
   using acc_t = typename MF::acc_t;
-  constexpr int WM = TM / 2, WN = TN / 2, SM = WM / 16, SN = WN / 16;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WM = TM / WGM, WN = TN / WGN, SM = WM / 16, SN = WN / 16;
   constexpr int SA = (sizeof(R) == 4) ? KC + 4 : KC + 2;  // A row stride: 4 x odd (f32), 2 x odd (f64)
   constexpr int SBS = TN + 16;
-  constexpr int NA = TM * KC / kThreads, NBV = KC * TN / kThreads;  // stage elements per thread
-  static_assert(TM * KC % kThreads == 0 && KC * TN % kThreads == 0, "stage split");
+  constexpr int NA = TM * KC / NT, NBV = KC * TN / NT;  // stage elements per thread
+  static_assert(TM * KC % NT == 0 && KC * TN % NT == 0 && WM % 16 == 0 && WN % 16 == 0, "stage split");
   __shared__ R Ar[TM * SA], Ai[TM * SA], Br[KC * SBS], Bi[KC * SBS];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -344,19 +345,19 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update(TlParams p, int K, int t
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
+      const int e = tid + NT * i, row = e / KC, kk = e - row * KC;
       const int r = r0 + row, k = k0 + kk;
       ra[i] = (r < t.N && k < Kend) ? W[(size_t)r * ld + k] : T{0, 0};
     }
 #pragma unroll
     for (int i = 0; i < NBV; ++i) {
-      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
+      const int e = tid + NT * i, kr = e / TN, col = e - kr * TN;
       const int k = k0 + kr, cc = c0 + col;
       rb[i] = (k < Kend && cc < cend) ? W[(size_t)k * ld + cc] : T{0, 0};
     }
   };
   fetch(K);
-  const int wm = wid & 1, wn = wid >> 1;
+  const int wm = wid % WGM, wn = wid / WGM;
   const int rw = r0 + wm * WM, cw = c0 + wn * WN;
   acc_t cr[SM][SN], ci[SM][SN];
 #pragma unroll
@@ -372,13 +373,13 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update(TlParams p, int K, int t
     __syncthreads();  // the previous stage is consumed
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
+      const int e = tid + NT * i, row = e / KC, kk = e - row * KC;
       Ar[row * SA + kk] = ra[i].x;
       Ai[row * SA + kk] = ra[i].y;
     }
 #pragma unroll
     for (int i = 0; i < NBV; ++i) {
-      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
+      const int e = tid + NT * i, kr = e / TN, col = e - kr * TN;
       Br[kr * SBS + col] = rb[i].x;
       Bi[kr * SBS + col] = rb[i].y;
     }
@@ -911,7 +912,10 @@ struct UpdShape<float> {
   template <int S>
   static void launch(hipStream_t s, dim3 g, const TlParams& p, int K, int tm, int tn, int cb, int ce) {
     if (S == 0) hipLaunchKernelGGL((k_tl_update<float, 128, 64, 16, 2>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
-    else hipLaunchKernelGGL((k_tl_update<float, 64, 64, 16, 3>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
+    else if (S == 1) hipLaunchKernelGGL((k_tl_update<float, 64, 64, 16, 3>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
+    else if (S == 2)
+      hipLaunchKernelGGL((k_tl_update<float, 128, 64, 16, 2, 4, 2>), g, dim3(512), 0, s, p, K, tm, tn, cb, ce);
+    else hipLaunchKernelGGL((k_tl_update<float, 128, 128, 16, 1, 4, 2>), g, dim3(512), 0, s, p, K, tm, tn, cb, ce);
   }
 };
 template <>
@@ -919,7 +923,10 @@ struct UpdShape<double> {
   template <int S>
   static void launch(hipStream_t s, dim3 g, const TlParams& p, int K, int tm, int tn, int cb, int ce) {
     if (S == 0) hipLaunchKernelGGL((k_tl_update<double, 128, 64, 8, 2>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
-    else hipLaunchKernelGGL((k_tl_update<double, 64, 64, 8, 3>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
+    else if (S == 1) hipLaunchKernelGGL((k_tl_update<double, 64, 64, 8, 3>), g, dim3(kThreads), 0, s, p, K, tm, tn, cb, ce);
+    else if (S == 2)
+      hipLaunchKernelGGL((k_tl_update<double, 128, 64, 8, 2, 4, 2>), g, dim3(512), 0, s, p, K, tm, tn, cb, ce);
+    else hipLaunchKernelGGL((k_tl_update<double, 128, 128, 8, 1, 4, 2>), g, dim3(512), 0, s, p, K, tm, tn, cb, ce);
   }
 };
 }  // namespace
@@ -957,20 +964,26 @@ hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax, int cb, 
   const int mr = nmax - K;                      // bounds of every item's trailing block
   const int nc = std::min(ncols - K, ce) - cb;  // and of this launch's column range
   if (mr <= 0 || nc <= 0) return hipSuccess;
-  const int TM = p.shape == 1 ? 64 : 128, TN = 64;
+  const bool split = p.mixed && p.half == PXD_HALF_BF16;  // split-BF16 kernels: 128 x 64 or 64 x 64 only
+  const int shape = (split && p.shape > 1) ? 0 : p.shape;
+  const int TM = shape == 1 ? 64 : 128, TN = shape == 3 ? 128 : 64;
   const int tiles_m = (mr + TM - 1) / TM, tiles_n = (nc + TN - 1) / TN;
   const int gx = (tiles_m * tiles_n + 7) / 8 * 8;  // a multiple of 8: the XCD grouping needs it
   const dim3 g(gx, p.B);
-  if (p.mixed && p.half == PXD_HALF_BF16) {
-    if (p.shape == 1)
+  if (split) {
+    if (shape == 1)
       hipLaunchKernelGGL((k_tl_update_bf16x3<64, 64, 3>), g, dim3(kThreads), 0, s, p, K, tiles_m, tiles_n, cb, ce);
     else
       hipLaunchKernelGGL((k_tl_update_bf16x3<128, 64, 2>), g, dim3(kThreads), 0, s, p, K, tiles_m, tiles_n, cb, ce);
   } else if (p.mixed) {
-    if (p.shape == 1) UpdShape<float>::launch<1>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+    if (shape == 1) UpdShape<float>::launch<1>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+    else if (shape == 2) UpdShape<float>::launch<2>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+    else if (shape == 3) UpdShape<float>::launch<3>(s, g, p, K, tiles_m, tiles_n, cb, ce);
     else UpdShape<float>::launch<0>(s, g, p, K, tiles_m, tiles_n, cb, ce);
   } else {
-    if (p.shape == 1) UpdShape<double>::launch<1>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+    if (shape == 1) UpdShape<double>::launch<1>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+    else if (shape == 2) UpdShape<double>::launch<2>(s, g, p, K, tiles_m, tiles_n, cb, ce);
+    else if (shape == 3) UpdShape<double>::launch<3>(s, g, p, K, tiles_m, tiles_n, cb, ce);
     else UpdShape<double>::launch<0>(s, g, p, K, tiles_m, tiles_n, cb, ce);
   }
   return hipGetLastError();

@@ -80,7 +80,7 @@ def test_autotune_picks_a_measured_configuration(tmp_path):
     rep = ev.autotune(base, off, cells, n_reps=2)
     # persistent path: workgroups per CU x sub-panel width x item order;
     # tiled path: block-column width x update tile x item order
-    assert len(rep) == 16
+    assert len(rep) == 24
     assert [r["ms"] for r in rep] == sorted(r["ms"] for r in rep)
     assert all(r["ms"] > 0 for r in rep)
     pers = [r for r in rep if r["lu_path"] == pxd.PATH_PERSISTENT]
@@ -88,7 +88,7 @@ def test_autotune_picks_a_measured_configuration(tmp_path):
     assert {(r["wg_per_cu"], r["half_subpanel"], r["schedule"]) for r in pers} == set(
         itertools.product((1, 2), (0, 1), (1, 2)))
     assert {(r["tile_kb"], r["tile_shape"], r["schedule"]) for r in tiled} == set(
-        itertools.product((64, 128), (1, 2), (1, 2)))
+        itertools.product((64, 128), (1, 2, 3, 4), (1, 2)))
     path = str(tmp_path / "tune.txt")
     ev.tune_save(path)
     lines = [l.split() for l in open(path) if not l.startswith("#")]
@@ -124,7 +124,7 @@ def test_autotune_keeps_fixed_options():
     pers = [r for r in rep if r["lu_path"] == pxd.PATH_PERSISTENT]
     assert sorted(r["wg_per_cu"] for r in pers) == [1, 2]
     assert sorted((r["tile_kb"], r["tile_shape"]) for r in rep if r["lu_path"] == pxd.PATH_TILED) == [
-        (64, 1), (64, 2), (128, 1), (128, 2)]
+        (64, 1), (64, 2), (64, 3), (64, 4), (128, 1), (128, 2), (128, 3), (128, 4)]
     assert all(r["half_subpanel"] == 0 and r["schedule"] == pxd.SCHED_FREQ_MAJOR for r in rep)
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     S_o, F_o = search.sweep(st, Z, base, off, cells, freqs)
@@ -133,8 +133,8 @@ def test_autotune_keeps_fixed_options():
     # a fixed path and block width leave only the other choices
     ev, _ = make_evaluator(spec, Z, freqs, precision=pxd.PREC_FP64, lu_path=pxd.PATH_TILED, tile_kb=128)
     rep = ev.autotune(base, off, cells)
-    assert {(r["lu_path"], r["tile_kb"]) for r in rep} == {(pxd.PATH_TILED, 128)} and len(rep) == 4
-    assert {(r["tile_shape"], r["schedule"]) for r in rep} == set(itertools.product((1, 2), (1, 2)))
+    assert {(r["lu_path"], r["tile_kb"]) for r in rep} == {(pxd.PATH_TILED, 128)} and len(rep) == 8
+    assert {(r["tile_shape"], r["schedule"]) for r in rep} == set(itertools.product((1, 2, 3, 4), (1, 2)))
     S, F, status, am = ev.evaluate_flips(base, off, cells)
     check(S, F, S_o, F_o, pxd.PREC_FP64)
     ev.close()

@@ -66,7 +66,7 @@ def test_tiled_matches_oracle_and_persistent_path(name, prec, kb, shape):
         assert stats["fallbacks"] == 0 and stats["ir_iterations"] >= stats["items"]
 
 
-@pytest.mark.parametrize("shape", [1, 2])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
 @pytest.mark.parametrize("prec", [pxd.PREC_FP64, pxd.PREC_MIXED32])
 @pytest.mark.parametrize("nx,layers,p", [(11, 2, 0.6), (16, 2, 0.7), (26, 1, 0.9)])
 def test_tiled_sizes_span_several_tiles(prec, nx, layers, p, shape):
