@@ -356,6 +356,145 @@ def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False, graph=Fa
     return out
 
 
+def search_leg(args, pxd, torch):
+    """The surrogate-pruned search at its working size against exhaustive
+    steepest descent over every single flip, from the same start map, on the
+    24 x 24 x 3 stack (101 frequencies); exact solves in the complex64 +
+    FP64 refinement form.
+    1. Exhaustive descent: every step solves all 1,728 single flips.  Its
+       first step's exact S (1,728 maps x 101 frequencies, about 175,000
+       (map, frequency) solves) is the surrogate's training set (10 % held
+       out), encoded on the device.
+    2. Training: BF16 products, AdamW, batches of 64; held-out loss and the
+       rank correlation of predicted and exact FoM on the held-out maps.
+    3. Pruned descent: each step the surrogate ranks all 1,728 singles and
+       1,492,128 pairs, its top 32 are solved exactly and the best strict
+       improvement is accepted; when none improves every single flip is
+       solved exactly (fallback); every exact solve fine-tunes the network.
+    Reported: FoM, wall time and exact solves after each step of both."""
+    from paper_2412_17617_amd.tree_search import descent
+
+    dev = torch.device("cuda:0")
+    spec = get_spec("stress24")
+    pb = pxd.Problem.from_spec(spec)
+    ev = pxd.Evaluator(device=0, precision=pxd.PREC_MIXED32, ir_max_iter=args.ir_max)
+    ev.load_problem(pb, spec.z0)
+    ev.load_parent_problem(pb, spec.freqs)
+    ev.set_fom_paper()
+    n = spec.n_cells
+    s_off, s_cells = np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32)
+    start = spec.base_map()
+    entries = ((0, 0), (1, 0), (2, 0), (2, 1))
+    sur = pxd.Surrogate(spec.n_layers, spec.ny, spec.nx, spec.freqs, spec.freqs[0], spec.freqs[-1],
+                        entries=entries, precision=pxd.SUR_BF16, max_batch=2048)
+    sur.init_params(4)
+    first = {}
+
+    def keep_first(maps, S):
+        if not first:
+            first["maps"], first["S"] = maps, S
+
+    t0 = time.time()
+    ex = descent(ev, start, s_off, s_cells, args.search_steps, learn=keep_first)
+    t_ex = time.time() - t0
+    log(f"[search24] exhaustive: FoM {ex.start_fom:.4g} -> {ex.fom:.4g} in "
+        f"{len(ex.trace)} steps, {ex.exact_solves} exact solves, {t_ex:.0f} s")
+    # training set: the first exhaustive step's exact solves
+    maps, S = first["maps"], first["S"]
+    t_S = torch.from_numpy(np.ascontiguousarray(np.stack([S.real, S.imag], -1))).to(dev)
+    tgt = torch.empty((len(maps), spec.n_freq, 3 * len(entries)), dtype=torch.float32, device=dev)
+    sur.encode_device(t_S, tgt)
+    del t_S
+    t_maps = torch.from_numpy(maps).to(dev)
+    perm = np.random.default_rng(4).permutation(len(maps))
+    n_held = len(maps) // 10
+    held, train = perm[:n_held], perm[n_held:]
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+
+    def held_loss():
+        hi = torch.from_numpy(held).to(dev)
+        sur.gradient(t_maps[hi[:512]], tgt[hi[:512]], None, loss)
+        return float(loss.item())
+
+    def fit(idx, steps, lr, seed):
+        rng = np.random.default_rng(seed)
+        for st in range(steps):
+            b = torch.from_numpy(rng.choice(idx, 64, replace=len(idx) < 64)).to(dev)
+            sur.train_step(t_maps[b], tgt[b], lr=lr, weight_decay=1e-4)
+
+    loss0 = held_loss()
+    t1 = time.time()
+    fit(train, args.search_train_steps, 2e-3, 5)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    loss1 = held_loss()
+    # ranking quality on the held-out single flips of the start map
+    cand = maps ^ start[None, :]
+    h_cells = np.array([int(np.nonzero(cand[i])[0][0]) for i in held], np.int32)
+    fp = torch.empty(len(held), dtype=torch.float64, device=dev)
+    sur.rank(ev, torch.from_numpy(start).to(dev), torch.from_numpy(np.arange(len(held) + 1, dtype=np.int32)).to(dev),
+             torch.from_numpy(h_cells).to(dev), 0, fp, None)
+    _, F_exact, _, _ = ev.evaluate_flips(start, np.arange(len(held) + 1, dtype=np.int32), h_cells, want_S=False)
+    ra = np.argsort(np.argsort(fp.cpu().numpy()))
+    rb = np.argsort(np.argsort(F_exact))
+    spearman = float(np.corrcoef(ra, rb)[0, 1])
+    log(f"[search24] surrogate trained on {len(train)} maps x {spec.n_freq} frequencies in {t_train:.1f} s: "
+        f"held-out loss {loss0:.3g} -> {loss1:.3g}, rank correlation {spearman:.3f}")
+    # pruned descent: singles and pairs ranked, top 32 exact, singles as fallback
+    iu, ju = np.triu_indices(n, 1)
+    a_off = np.concatenate([s_off, n + 2 * np.arange(1, len(iu) + 1)]).astype(np.int32)
+    a_cells = np.concatenate([s_cells, np.stack([iu, ju], 1).ravel()]).astype(np.int32)
+    t_aoff, t_acells = torch.from_numpy(a_off).to(dev), torch.from_numpy(a_cells).to(dev)
+    fp_all = torch.empty(len(a_off) - 1, dtype=torch.float64, device=dev)
+    top = torch.empty(32, dtype=torch.int32, device=dev)
+
+    def ranker(m, o, c):
+        sur.rank(ev, torch.from_numpy(m).to(dev), t_aoff, t_acells, 32, fp_all, top)
+        torch.cuda.synchronize()
+        return top.cpu().numpy()
+
+    seen_m, seen_t = [t_maps[torch.from_numpy(train).to(dev)]], [tgt[torch.from_numpy(train).to(dev)]]
+
+    def learn(new_maps, S_new):
+        tS = torch.from_numpy(np.ascontiguousarray(np.stack([S_new.real, S_new.imag], -1))).to(dev)
+        tt = torch.empty((len(new_maps), spec.n_freq, 3 * len(entries)), dtype=torch.float32, device=dev)
+        sur.encode_device(tS, tt)
+        seen_m.append(torch.from_numpy(new_maps).to(dev))
+        seen_t.append(tt)
+        allm, allt = torch.cat(seen_m), torch.cat(seen_t)
+        rng = np.random.default_rng(len(allm))
+        for _ in range(args.search_finetune_steps):  # half of each batch from the newest solves
+            b_new = torch.from_numpy(rng.integers(len(allm) - len(new_maps), len(allm), 32)).to(dev)
+            b_old = torch.from_numpy(rng.integers(0, len(allm), 32)).to(dev)
+            b = torch.cat([b_new, b_old])
+            sur.train_step(allm[b], allt[b], lr=5e-4, weight_decay=1e-4)
+
+    t2 = time.time()
+    pr = descent(ev, start, a_off, a_cells, args.search_steps, ranker=ranker, top_k=32, fallback=(s_off, s_cells),
+                 learn=learn)
+    t_pr = time.time() - t2
+    log(f"[search24] pruned: FoM {pr.fom:.4g} in {len(pr.trace)} steps ({[t[3] for t in pr.trace]}), "
+        f"{pr.exact_solves} exact solves, {t_pr:.0f} s (+ {t_train:.0f} s training)")
+    sur.close()
+    ev.close()
+    torch.cuda.empty_cache()
+
+    def traj(r):
+        return [{"s": round(t[0], 2), "exact_solves": int(t[1]), "fom": float(t[2]), "step": t[3]} for t in r.trace]
+
+    return {"workload": "24x24x3 stack, 101 frequencies; start = the workload's Bernoulli(0.5) map",
+            "exact_form": "complex64 LU + FP64 refinement (tiled, lock step)",
+            "start_fom": ex.start_fom,
+            "exhaustive": {"moves": int(n), "final_fom": ex.fom, "exact_solves": ex.exact_solves, "seconds": t_ex,
+                           "trajectory": traj(ex)},
+            "surrogate": {"train_maps": int(len(train)), "held_out_maps": int(n_held), "frequencies": spec.n_freq,
+                          "train_steps": args.search_train_steps, "batch": 64, "train_seconds": t_train,
+                          "held_out_loss_before": loss0, "held_out_loss_after": loss1,
+                          "held_out_rank_correlation": spearman},
+            "pruned": {"ranked_moves": int(len(a_off) - 1), "verified": 32, "final_fom": pr.fom,
+                       "exact_solves": pr.exact_solves, "seconds": t_pr, "trajectory": traj(pr)}}
+
+
 def lowrank_leg(args, pxd, spec):
     """All single flips of the 20 x 20 x 2 map through the low-rank flip
     evaluation (FP64, from the cached inverse of the base map), host buffers."""
@@ -450,8 +589,12 @@ def main():
                          "counters (FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--ir-max", type=int, default=10)
     ap.add_argument("--leg-steps", type=int, default=1)
+    ap.add_argument("--search-steps", type=int, default=4, help="search24 leg: descent steps per method")
+    ap.add_argument("--search-train-steps", type=int, default=1500, help="search24 leg: initial training steps")
+    ap.add_argument("--search-finetune-steps", type=int, default=40, help="search24 leg: steps per new solve batch")
     ap.add_argument("--legs", default="stress24,batched20,surrogate,lowrank",
-                    help="comma list of extra legs (stress24, batched20, surrogate, lowrank) or 'none'")
+                    help="comma list of extra legs (stress24, batched20, surrogate, lowrank; search24, the "
+                         "surrogate-pruned against exhaustive search, about 8 minutes, is not in the default) or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -506,6 +649,8 @@ def main():
                                        "batched20", tune=True, graph=True)
     if "surrogate" in legs:
         extra["surrogate"] = surrogate_leg(args, pxd, get_spec("stress24"), torch)
+    if "search24" in legs:
+        extra["search24"] = search_leg(args, pxd, torch)
     if "lowrank" in legs:
         extra["lowrank"] = lowrank_leg(args, pxd, get_spec("batched20"))
 

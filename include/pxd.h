@@ -463,6 +463,12 @@ int pxd_sur_train_step(pxd_sur* s, void* stream, int32_t B, const uint8_t* maps,
  * ties to the lower index (device int32). */
 int pxd_sur_rank(pxd_sur* s, const pxd_ctx* ctx, void* stream, const uint8_t* base_map, int32_t n_cand,
                  const int32_t* offsets, const int32_t* cells, int32_t k, double* fom_pred, int32_t* top);
+/* Training targets from exact S on the device: S is n x F x P x P complex128
+ * (interleaved, the evaluator's S layout); target n x F x (3 n_entries)
+ * float32: per predicted entry ln max(|S_ij|, 1e-30), cos arg S_ij,
+ * sin arg S_ij (the outputs above).  Device pointers on `stream`; entries
+ * beyond P give PXD_ESHAPE. */
+int pxd_sur_encode(pxd_sur* s, void* stream, int32_t n, const double* S, int32_t P, float* target);
 
 #ifdef __cplusplus
 }

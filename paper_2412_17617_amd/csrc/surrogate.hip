@@ -517,6 +517,24 @@ struct Tensor {
 
 }  // namespace
 
+// Training targets from exact S (n x F x P x P complex128): per (map,
+// frequency) and predicted entry (i, j): ln max(|S_ij|, 1e-30) and the unit
+// phasor S_ij / |S_ij|, in entry order.
+__global__ void k_encode(const double2* __restrict__ S, int n, int F, int P, int n_ent, const int* __restrict__ ei,
+                         const int* __restrict__ ej, float* __restrict__ out) {
+  const size_t total = (size_t)n * F * n_ent;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+    const int e = (int)(q % n_ent);
+    const size_t bf = q / n_ent;
+    const double2 v = S[bf * P * P + (size_t)ei[e] * P + ej[e]];
+    const double a = fmax(sqrt(v.x * v.x + v.y * v.y), 1e-30);
+    float* o = out + bf * (3 * n_ent) + 3 * e;
+    o[0] = (float)log(a);
+    o[1] = (float)(v.x / a);
+    o[2] = (float)(v.y / a);
+  }
+}
+
 struct pxd_sur {
   pxd_sur_config cfg{};
   std::string err;
@@ -919,6 +937,22 @@ int pxd_sur_rank(pxd_sur* s, const pxd_ctx* ctx, void* stream, const uint8_t* ba
     hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, fom_pred, n_cand, k, top);
     SURCHK(s, hipGetLastError());
   }
+  return PXD_OK;
+}
+
+int pxd_sur_encode(pxd_sur* s, void* stream, int32_t n, const double* S, int32_t P, float* target) {
+  if (!s) return pxd::set_thread_error(PXD_EINVAL, "surrogate is NULL");
+  if (n < 0 || (n > 0 && (!S || !target)) || P < 1) return s->fail(PXD_EINVAL, "invalid encoding arguments");
+  for (int k = 0; k < s->cfg.n_entries; ++k)
+    if (s->cfg.entry_i[k] >= P || s->cfg.entry_j[k] >= P) return s->fail(PXD_ESHAPE, "predicted entry beyond P");
+  if (n == 0) return PXD_OK;
+  SURCHK(s, hipSetDevice(s->cfg.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t total = (size_t)n * s->F * s->cfg.n_entries;
+  const int* ei = s->ent.as<int>();
+  hipLaunchKernelGGL(k_encode, dim3((unsigned)std::min<size_t>((total + 255) / 256, 4096)), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(S), n, s->F, P, s->cfg.n_entries, ei, ei + 4, target);
+  SURCHK(s, hipGetLastError());
   return PXD_OK;
 }
 

@@ -469,6 +469,7 @@ _SIGS.update({
     "pxd_sur_gradient": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "pxd_sur_train_step": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, C.POINTER(AdamW), _VP]),
     "pxd_sur_rank": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP]),
+    "pxd_sur_encode": (C.c_int, [_VP, _VP, C.c_int32, _VP, C.c_int32, _VP]),
 })
 
 
@@ -537,6 +538,12 @@ class Surrogate:
     def rank(self, evaluator, base_map, offsets, cells, k, fom_pred, top, stream=None):
         self._c(lib().pxd_sur_rank(self._h, evaluator._h, self._s(stream), self._d(base_map), offsets.numel() - 1,
                                    self._d(offsets), self._d(cells), k, self._d(fom_pred), self._d(top)))
+
+    def encode_device(self, S, target, stream=None):
+        """Training targets on the device from exact S (torch CUDA tensors:
+        S n x F x P x P x 2 float64, target n x F x 3 n_entries float32)."""
+        n, P = S.shape[0], S.shape[2]
+        self._c(lib().pxd_sur_encode(self._h, self._s(stream), n, self._d(S), P, self._d(target)))
 
     @staticmethod
     def encode(S, entries=((0, 0), (1, 0), (2, 0))):

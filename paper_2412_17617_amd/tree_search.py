@@ -22,6 +22,10 @@ never selected.  Solving the trees
 by the low-rank flip evaluation from the current map's inverse (``lowrank``)
 is switched off: its one GPU run inside this driver made a memory fault
 whose cause has not been shown, so the option raises.
+
+Also here: steepest descent over a fixed move set (single and pair flips),
+exhaustive or pruned by a ranker with the exact fallback (``descent``), and
+the classical one-pixel-at-a-time direct binary search (``sequential_dbs``).
 """
 
 from __future__ import annotations
@@ -168,3 +172,120 @@ class TreeSearch:
                         D += 1
             res.trace.append((res.evaluations, F))
         return res
+
+
+# ---------------------------------------------------------------- descent and DBS
+
+
+@dataclass
+class DescentResult:
+    fom: float
+    best_map: np.ndarray
+    exact_solves: int
+    trace: list = field(default_factory=list)  # per step: (seconds, exact solves, FoM, how the step ended)
+    start_fom: float = np.inf
+
+
+def _subset(offs, cells, idx):
+    sub = np.zeros(len(idx) + 1, np.int32)
+    sub[1:] = np.cumsum([offs[i + 1] - offs[i] for i in idx])
+    sc = np.concatenate([cells[offs[i]:offs[i + 1]] for i in idx]).astype(np.int32) if len(idx) else \
+        np.zeros(0, np.int32)
+    return sub, sc
+
+
+def descent(evaluator, start_map, offs, cells, max_steps, ranker=None, top_k=32, fallback=None, learn=None,
+            clock=None):
+    """Steepest descent over a fixed move set (flip lists relative to the
+    current map, CSR offs / cells), accepting only strict improvements
+    (Algorithm 1's accept rule at depth one, with pair moves when the set
+    holds them).
+
+    Exhaustive (ranker None): every move is solved exactly each step.
+    Pruned: ranker(map, offs, cells) returns move indices best first; only
+    its top_k are solved, and when none of them improves, the moves of
+    `fallback` (CSR pair (offs, cells); default: the whole move set) are
+    solved before the search stops, so the exact solve stays both the
+    judge of every accepted move and the fallback.  learn(maps, S) receives
+    every exact solve (candidate maps and their S) for fine-tuning.  Failed
+    candidates (negative status) are never accepted.  Stops at a local
+    minimum of the solved moves or after max_steps accepted moves."""
+    import time
+
+    clock = clock or time.perf_counter
+    t0 = clock()
+    m = np.array(start_map, np.uint8)
+    _, F0, st0, _ = evaluator.evaluate_flips(m, np.array([0, 0], np.int32), np.zeros(0, np.int32), want_S=False)
+    F = float(F0[0]) if st0[0] >= 0 else np.inf
+    res = DescentResult(F, m.copy(), 1, start_fom=F)
+
+    def solve(o, c):
+        S, Fc, st, _ = evaluator.evaluate_flips(m, o, c, want_S=learn is not None)
+        res.exact_solves += len(o) - 1
+        if learn is not None:
+            maps = np.repeat(m[None, :], len(o) - 1, axis=0)
+            for r in range(len(o) - 1):
+                maps[r, c[o[r]:o[r + 1]]] ^= 1
+            learn(maps, S)
+        return TreeSearch._valid(Fc, st)
+
+    for _ in range(max_steps):
+        how = "exhaustive"
+        if ranker is None:
+            Fc = solve(offs, cells)
+            o_acc, c_acc = offs, cells
+        else:
+            pick = np.asarray(ranker(m, offs, cells))[:top_k]
+            o_acc, c_acc = _subset(offs, cells, pick)
+            Fc = solve(o_acc, c_acc)
+            how = "verified"
+            if not (np.min(Fc) < F):
+                how = "fallback"
+                if fallback is not None:
+                    o_acc, c_acc = fallback
+                    Fc = solve(o_acc, c_acc)
+                else:  # the moves not verified yet
+                    rest = np.setdiff1d(np.arange(len(offs) - 1), pick)
+                    if len(rest):
+                        both = np.concatenate([pick, rest])
+                        o_r, c_r = _subset(offs, cells, rest)
+                        Fc = np.concatenate([Fc, solve(o_r, c_r)])
+                        o_acc, c_acc = _subset(offs, cells, both)
+        k = int(np.argmin(Fc))
+        if not (np.isfinite(Fc[k]) and Fc[k] < F):
+            res.trace.append((clock() - t0, res.exact_solves, F, how + ", local minimum"))
+            break
+        m = m.copy()
+        m[c_acc[o_acc[k]:o_acc[k + 1]]] ^= 1
+        F = float(Fc[k])
+        res.fom, res.best_map = F, m.copy()
+        res.trace.append((clock() - t0, res.exact_solves, F, how))
+    return res
+
+
+def sequential_dbs(evaluator, start_map, order, sweeps=1):
+    """Classical direct binary search (Section III-A): visit the pixels in
+    `order`, toggle one, keep the toggle if the FoM improves strictly and
+    undo it otherwise; one exact solve per visit.  Returns a DescentResult
+    whose trace holds (visits, exact solves, FoM, "kept"/"undone")."""
+    m = np.array(start_map, np.uint8)
+    _, F0, st0, _ = evaluator.evaluate_flips(m, np.array([0, 0], np.int32), np.zeros(0, np.int32), want_S=False)
+    F = float(F0[0]) if st0[0] >= 0 else np.inf
+    res = DescentResult(F, m.copy(), 1, start_fom=F)
+    visits = 0
+    for _ in range(sweeps):
+        for j in order:
+            _, Fc, st, _ = evaluator.evaluate_flips(m, np.array([0, 1], np.int32), np.array([j], np.int32),
+                                                    want_S=False)
+            res.exact_solves += 1
+            visits += 1
+            Fj = TreeSearch._valid(Fc, st)[0]
+            if Fj < F:
+                m = m.copy()
+                m[j] ^= 1
+                F = float(Fj)
+                res.fom, res.best_map = F, m.copy()
+                res.trace.append((visits, res.exact_solves, F, "kept"))
+            else:
+                res.trace.append((visits, res.exact_solves, F, "undone"))
+    return res

@@ -21,6 +21,7 @@ import pytest
 
 from oracle import surrogate as osur
 from paper_2412_17617_amd import pxd
+from paper_2412_17617_amd.tree_search import descent
 
 from sur_common import init_params, random_maps
 
@@ -323,45 +324,12 @@ def test_global_search_with_the_surrogate(world, trained):
     assert r1 > r0 + 0.3
 
 
-def greedy(ev, m0, first_of, max_steps=40, learn=None):
-    """Steepest descent over every single and pair flip, accepting strict
-    improvements only (Algorithm 1 with depth-two moves).  first_of(m, off,
-    cells) -> candidates to solve exactly first; when none of them improves,
-    the rest are solved before the search stops, so it always ends in a true
-    local minimum.  Returns (final FoM, exact solves)."""
+def move_set():
+    """Every single and pair flip of the 16 cells (136 moves), CSR."""
     pairs = [(a,) for a in range(16)] + [(a, b) for a in range(16) for b in range(a + 1, 16)]
     off = np.zeros(len(pairs) + 1, np.int32)
     off[1:] = np.cumsum([len(q) for q in pairs])
-    cells = np.concatenate(pairs).astype(np.int32)
-    m = m0.copy()
-    _, F, _, _ = ev.evaluate_maps(m[None, :])
-    cur, n_eval = F[0], 1
-    for _ in range(max_steps):
-        first = np.asarray(first_of(m, off, cells))
-        rest = np.setdiff1d(np.arange(len(pairs)), first)
-        moved = False
-        for group in (first, rest):
-            if len(group) == 0:
-                continue
-            sub_off = np.zeros(len(group) + 1, np.int32)
-            sub_off[1:] = np.cumsum([len(pairs[g]) for g in group])
-            sub_cells = np.concatenate([pairs[g] for g in group]).astype(np.int32)
-            S, F, _, am = ev.evaluate_flips(m, sub_off, sub_cells)
-            n_eval += len(group)
-            if learn is not None:
-                maps = np.repeat(m[None, :], len(group), axis=0)
-                for r, g in enumerate(group):
-                    for cidx in pairs[g]:
-                        maps[r, cidx] ^= 1
-                learn(maps, S)
-            if F[am] < cur:
-                for cidx in pairs[group[am]]:
-                    m[cidx] ^= 1
-                cur, moved = F[am], True
-                break
-        if not moved:
-            break
-    return cur, n_eval
+    return off, np.concatenate(pairs).astype(np.int32)
 
 
 K_VERIFY = 48
@@ -396,14 +364,40 @@ def test_pruned_search_matches_exhaustive_search(world, trained):
         train_more(s, np.concatenate([base_maps[:2048], np.tile(new_m, (rep, 1))]),
                    np.concatenate([base_target[:2048], np.tile(new_t, (rep, 1, 1))]), 40, seed=len(new_m))
 
+    off, cells = move_set()
     tot_ex = tot_pr = 0
     for seed in range(4):
         start = ((np.random.default_rng(900 + seed).random(16)) < 0.5).astype(np.uint8)
-        f_ex, n_ex = greedy(ev, start, lambda m, o, c: np.arange(len(o) - 1))
-        f_pr, n_pr = greedy(ev, start, top_k, learn=learn)
-        print(f"start {seed}: exhaustive {f_ex:.6g} ({n_ex} exact solves), pruned {f_pr:.6g} ({n_pr})")
-        assert f_pr == f_ex
-        tot_ex += n_ex
-        tot_pr += n_pr
+        ex = descent(ev, start, off, cells, max_steps=40)
+        pr = descent(ev, start, off, cells, max_steps=40, ranker=top_k, top_k=K_VERIFY, learn=learn)
+        print(f"start {seed}: exhaustive {ex.fom:.6g} ({ex.exact_solves} exact solves), pruned {pr.fom:.6g} "
+              f"({pr.exact_solves}; steps {[t[3] for t in pr.trace]})")
+        assert pr.fom == ex.fom
+        assert all(t[3] != "exhaustive" for t in pr.trace)
+        tot_ex += ex.exact_solves
+        tot_pr += pr.exact_solves
     s.close()
     assert tot_pr < tot_ex
+
+
+def test_device_encoding_matches_host_encoding():
+    """pxd_sur_encode forms the training targets on the device from S in the
+    evaluator's layout: the same numbers as the host-side encode (float32
+    rounding), tiny entries clamped at 1e-30 alike."""
+    freqs = FREQS
+    entries = ((0, 0), (1, 0), (2, 0), (2, 1))
+    s = pxd.Surrogate(CFG.n_layers, CFG.ny, CFG.nx, freqs, freqs[0], freqs[-1], channels=CFG.channels,
+                      hidden=CFG.hidden, emb=CFG.emb, entries=entries, precision=pxd.SUR_FP32, max_batch=8)
+    rng = np.random.default_rng(3)
+    n, P = 5, 3
+    S = rng.normal(size=(n, len(freqs), P, P)) + 1j * rng.normal(size=(n, len(freqs), P, P))
+    S[0, 0, 2, 1] = 0.0
+    S *= np.exp(rng.uniform(-8, 0, size=S.shape))
+    t_S = torch.from_numpy(np.ascontiguousarray(np.stack([S.real, S.imag], -1))).to(DEV)
+    tgt = torch.empty((n, len(freqs), 3 * len(entries)), dtype=torch.float32, device=DEV)
+    s.encode_device(t_S, tgt)
+    torch.cuda.synchronize()
+    ref = pxd.Surrogate.encode(S, entries)
+    got = tgt.cpu().numpy()
+    s.close()
+    assert np.allclose(got, ref, rtol=1e-6, atol=1e-6), np.abs(got - ref).max()

@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from paper_2412_17617_amd.tree_search import TreeSearch
+from paper_2412_17617_amd.tree_search import TreeSearch, descent, sequential_dbs
 
 
 def test_tree_search_rejects_bad_depths():
@@ -86,6 +86,51 @@ def test_prefilter_falls_back_to_exact_solves():
     assert list(res.best_map) == [0, 0, 1, 0]
     # the verified leaf (state 1, FoM 11) failed, then the other two were solved
     assert res.trace[0] == (1 + 1 + 2, 5.0)
+
+
+def _singles(n):
+    return np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32)
+
+
+def test_exhaustive_descent_takes_the_steepest_move_each_step():
+    # FoM = 1 + sum of weights of the metal cells: the steepest move clears the
+    # heaviest remaining cell; four steps reach the empty map, the fifth finds
+    # no improving move
+    w = np.array([1.0, 4.0, 2.0, 3.0])
+    ev = _TableEvaluator(lambda m: 1.0 + float(w @ m))
+    offs, cells = _singles(4)
+    res = descent(ev, np.ones(4, np.uint8), offs, cells, max_steps=10)
+    assert [round(t[2], 9) for t in res.trace[:4]] == [7.0, 4.0, 2.0, 1.0]
+    assert res.trace[-1][3].endswith("local minimum") and res.fom == 1.0
+    assert res.exact_solves == 1 + 5 * 4 and list(res.best_map) == [0, 0, 0, 0]
+
+
+def test_pruned_descent_falls_back_and_never_accepts_a_failed_move():
+    w = np.array([1.0, 4.0, 2.0, 3.0])
+    start = np.ones(4, np.uint8)
+    bad = start.copy()
+    bad[1] = 0  # the steepest first move is a failed solve
+    ev = _TableEvaluator(lambda m: 1.0 + float(w @ m), bad=[bad])
+    offs, cells = _singles(4)
+    # the ranker puts the moves that improve most last: the one verified move
+    # (cell 0, the smallest weight) improves, so no fallback is needed
+    res = descent(ev, start, offs, cells, max_steps=1, ranker=lambda m, o, c: [0, 2, 3, 1], top_k=1)
+    assert res.trace[0][3] == "verified" and res.fom == 10.0 and res.exact_solves == 2
+    # a ranker that only offers a non-improving move: the exact fallback over
+    # the rest of the set runs and takes the best valid move (cell 3; cell 1 failed)
+    start2 = np.array([0, 1, 1, 1], np.uint8)
+    ev = _TableEvaluator(lambda m: 1.0 + float(w @ m), bad=[np.array([0, 0, 1, 1], np.uint8)])
+    res = descent(ev, start2, offs, cells, max_steps=1, ranker=lambda m, o, c: [0], top_k=1)
+    assert res.trace[0][3] == "fallback" and res.exact_solves == 1 + 1 + 3
+    assert list(res.best_map) == [0, 1, 1, 0] and res.fom == 7.0
+
+
+def test_sequential_dbs_keeps_only_improving_toggles():
+    w = np.array([1.0, -4.0, 2.0, -3.0])  # clearing cells 1 and 3 makes it worse
+    ev = _TableEvaluator(lambda m: 10.0 + float(w @ m))
+    res = sequential_dbs(ev, np.ones(4, np.uint8), [0, 1, 2, 3])
+    assert [t[3] for t in res.trace] == ["kept", "undone", "kept", "undone"]
+    assert list(res.best_map) == [0, 1, 0, 1] and res.fom == 3.0 and res.exact_solves == 5
 
 
 # ---------------------------------------------------------------- refinement rule
