@@ -118,7 +118,7 @@ def oracle_time(prepared, seconds, threads=None):
             pos = -np.ones(st.M, np.int64)
             pos[idx] = np.arange(len(idx))
             pl = search.port_lengths(st)
-            done, t0 = 0, time.perf_counter()
+            done, t0, c0 = 0, time.perf_counter(), time.process_time()
             while True:
                 for m in maps:
                     sel = st.active(m)
@@ -130,8 +130,9 @@ def oracle_time(prepared, seconds, threads=None):
                 el = time.perf_counter() - t0
                 if el >= seconds / len(prepared):
                     break
+            busy = (time.process_time() - c0) / el  # CPU seconds per second: the cores actually kept busy
             res[label] = {"value": 1.0 / (el / done * spec.n_freq), "unit": "evals/s", "cores": int(cores),
-                          "kind": "oracle",
+                          "cores_busy": round(busy, 2), "kind": "oracle",
                           "sample": f"{len(maps)} candidates x 1 frequency ({spec.freqs[fi] / 1e9:.3f} GHz), "
                                     f"{done} solves in {el:.1f} s, scaled x{spec.n_freq} frequencies per evaluation"}
     return res
@@ -278,7 +279,7 @@ def graph_rate(args, torch, ev, stream, inputs, n_max, eager, n_cand, label, mod
             "max_dS_vs_eager": dS, "argmin_equal_eager": am == eager["am"]}
 
 
-def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False, graph=False):
+def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False, graph=False, lu_path=0):
     """Single-flip candidates of a workload at every frequency, device
     buffers, one evaluator call per step (and, with `graph`, the same step as
     replays of a captured HIP graph)."""
@@ -292,7 +293,7 @@ def batch_leg(args, pxd, torch, spec, n_cand, modes, label, tune=False, graph=Fa
     t_base, t_off, t_cells = (torch.from_numpy(a).to(dev) for a in (base, off, cells))
     out = {"candidates": n_cand, "frequencies": spec.n_freq}
     for mode in modes:
-        ev = pxd.Evaluator(device=0, precision=PREC[mode], ir_max_iter=args.ir_max, half_subpanel=1)
+        ev = pxd.Evaluator(device=0, precision=PREC[mode], ir_max_iter=args.ir_max, half_subpanel=1, lu_path=lu_path)
         ev.load_problem(pb, spec.z0)
         ev.load_parent_problem(pb, spec.freqs)
         ev.set_fom_paper()
@@ -373,11 +374,12 @@ def search_leg(args, pxd, torch):
        solved exactly (fallback); every exact solve fine-tunes the network.
     Reported: FoM, wall time and exact solves after each step of both."""
     from paper_2412_17617_amd.tree_search import descent
+    from synth import get_spec
 
     dev = torch.device("cuda:0")
     spec = get_spec("stress24")
     pb = pxd.Problem.from_spec(spec)
-    ev = pxd.Evaluator(device=0, precision=pxd.PREC_MIXED32, ir_max_iter=args.ir_max)
+    ev = pxd.Evaluator(device=0, precision=pxd.PREC_MIXED32, ir_max_iter=args.ir_max, lu_path=pxd.PATH_TILED)
     ev.load_problem(pb, spec.z0)
     ev.load_parent_problem(pb, spec.freqs)
     ev.set_fom_paper()
@@ -393,6 +395,7 @@ def search_leg(args, pxd, torch):
     def keep_first(maps, S):
         if not first:
             first["maps"], first["S"] = maps, S
+        log(f"[search24] exhaustive: {len(maps)} moves solved exactly ({time.time() - t0:.0f} s)")
 
     t0 = time.time()
     ex = descent(ev, start, s_off, s_cells, args.search_steps, learn=keep_first)
@@ -456,6 +459,7 @@ def search_leg(args, pxd, torch):
     seen_m, seen_t = [t_maps[torch.from_numpy(train).to(dev)]], [tgt[torch.from_numpy(train).to(dev)]]
 
     def learn(new_maps, S_new):
+        log(f"[search24] pruned: {len(new_maps)} moves solved exactly ({time.time() - t2:.0f} s)")
         tS = torch.from_numpy(np.ascontiguousarray(np.stack([S_new.real, S_new.imag], -1))).to(dev)
         tt = torch.empty((len(new_maps), spec.n_freq, 3 * len(entries)), dtype=torch.float32, device=dev)
         sur.encode_device(tS, tt)
@@ -643,7 +647,7 @@ def main():
     extra = {}
     if "stress24" in legs:
         extra["stress24"] = batch_leg(args, pxd, torch, get_spec("stress24"), 64, ["fp64", "mixed32", "bf16x3"],
-                                      "stress24")
+                                      "stress24", lu_path=pxd.PATH_TILED)
     if "batched20" in legs:
         extra["batched20"] = batch_leg(args, pxd, torch, get_spec("batched20"), 800, ["fp64", "mixed32", "bf16x3"],
                                        "batched20", tune=True, graph=True)
