@@ -216,16 +216,38 @@ __device__ __forceinline__ void factor_panel(typename Cx<R>::T* __restrict__ W, 
           }
       }
       __syncthreads();
-      for (int r = c0 + sbw + tid; r < N; r += kThreads) {
-        T l[SB];
+      {
+        // rows below: the 32 lanes of a half-wave span a row's w2 columns
+        // (one contiguous segment per load and store; the row's L entries are
+        // broadcast loads), RU rows per half-wave and step, all their loads
+        // issued before any product
+        constexpr int RW = SB * (int)sizeof(R) / 4;  // register words of one row's L entries
+        constexpr int RU = RW >= 32 ? 1 : RW >= 16 ? 2 : RW >= 8 ? 4 : 8;
+        const int lane = tid & 63, wid = tid >> 6, t = lane & 31, half = lane >> 5;
+        const int step = 2 * kWaves;
+        T u[SB];
 #pragma unroll
-        for (int j = 0; j < SB; ++j) l[j] = (j < sbw) ? W[(size_t)r * ld + c0 + j] : T{0, 0};
-        T* row = W + (size_t)r * ld + c0 + sbw;
-        for (int t = 0; t < w2; ++t) {
-          T acc = row[t];
+        for (int j = 0; j < SB; ++j) u[j] = (t < w2 && j < sbw) ? sm.buf[NB * NB + j * NB + t] : T{0, 0};
+        for (int rb = c0 + sbw + 2 * wid + half; rb < N; rb += step * RU) {
+          T lv[RU][SB], v[RU];
 #pragma unroll
-          for (int j = 0; j < SB; ++j) acc = cfms(acc, l[j], sm.buf[NB * NB + j * NB + t]);
-          row[t] = acc;
+          for (int q = 0; q < RU; ++q) {
+            const int r = rb + q * step;
+            const bool ok = t < w2 && r < N;
+#pragma unroll
+            for (int j = 0; j < SB; ++j) lv[q][j] = (ok && j < sbw) ? W[(size_t)r * ld + c0 + j] : T{0, 0};
+            v[q] = ok ? W[(size_t)r * ld + c0 + sbw + t] : T{0, 0};
+          }
+#pragma unroll
+          for (int q = 0; q < RU; ++q) {
+            const int r = rb + q * step;
+            if (t < w2 && r < N) {
+              T acc{0, 0};
+#pragma unroll
+              for (int j = 0; j < SB; ++j) acc = cfms(acc, lv[q][j], u[j]);
+              W[(size_t)r * ld + c0 + sbw + t] = T{v[q].x + acc.x, v[q].y + acc.y};
+            }
+          }
         }
       }
       __syncthreads();
@@ -374,9 +396,9 @@ __device__ __forceinline__ void apply_swaps(T* __restrict__ W, int ld, int k, in
 // L21 fragments in registers while sweeping the block columns; the four waves
 // sweep the columns in the same order, so a U12 block is fetched from memory
 // once and served to the other waves from cache.  Each 32 x 32 output tile
-// issues its loads (C into the accumulators, the U12 fragments) before its
-// 128 MFMAs, so the two waves sharing a SIMD overlap one tile's memory
-// latency with the other's arithmetic.
+// issues its U12 fragment loads before its 128 MFMAs (the products are
+// summed from zero and added to C once at the end), so the two waves sharing
+// a SIMD overlap one tile's memory latency with the other's arithmetic.
 template <typename R>
 __device__ __forceinline__ void trailing_update(typename Cx<R>::T* __restrict__ W, int ld, int k, int kb, int N,
                                                 int c0, int ncols) {
