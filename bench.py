@@ -131,7 +131,8 @@ def oracle_time(prepared, seconds, threads=None):
                 if el >= seconds / len(prepared):
                     break
             busy = (time.process_time() - c0) / el  # CPU seconds per second: the cores actually kept busy
-            res[label] = {"value": 1.0 / (el / done * spec.n_freq), "unit": "evals/s", "cores": int(cores),
+            res[label] = {"value": 1.0 / (el / done * spec.n_freq), "unit": "evals/s",
+                          "cores": max(1, int(round(busy))), "blas_threads": int(cores),
                           "cores_busy": round(busy, 2), "kind": "oracle",
                           "sample": f"{len(maps)} candidates x 1 frequency ({spec.freqs[fi] / 1e9:.3f} GHz), "
                                     f"{done} solves in {el:.1f} s, scaled x{spec.n_freq} frequencies per evaluation"}
@@ -767,7 +768,9 @@ def main():
         except OSError:
             pass
         out["cpu_baseline"] = dict(cb["headline"])
-        out["cpu_baseline"].update({"nproc": os.cpu_count(), "cpu_model": model, "machine": platform.machine(),
+        affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+        out["cpu_baseline"].update({"nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": model,
+                                    "machine": platform.machine(),
                                     "one_thread": cb1["headline"],
                                     "other_workloads": {k: v for k, v in cb.items() if k != "headline"}})
     pool.shutdown()

@@ -96,13 +96,19 @@ typedef struct pxd_geometry {
   int32_t n_vias;
   const int32_t* via_x;
   const int32_t* via_y;
+  int32_t sub;         /* squares per pixel side (0 or 1: 2 triangles per pixel; 2: 8; 3: 18), each square
+                          split into two right triangles, diagonals alternating over the squares
+                          (the mesh study of Section V); feeds attach to square sub / 2 of their side */
 } pxd_geometry;
 
 typedef struct pxd_problem pxd_problem;
 
-/* Build mesh and RWG functions in canonical order: inner (cell order),
- * inter-pixel horizontal then vertical, pixel-port, via, feed diagonals, port
- * edges last (port order).  *out is owned by the caller (pxd_problem_destroy). */
+/* Build mesh and RWG functions in canonical order: inner (cell order; within
+ * a pixel by the edge's midpoint, y first), inter-pixel horizontal then
+ * vertical (each pixel pair's squares in order along the side), pixel-port,
+ * via (per via: top junctions, then diagonals and sub-strip sides, then
+ * bottom junctions, each by position), feed diagonals, port edges last (port
+ * order).  *out is owned by the caller (pxd_problem_destroy). */
 int pxd_problem_create(const pxd_geometry* g, pxd_problem** out);
 void pxd_problem_destroy(pxd_problem* p);
 /* Parent size M, cell count and port count. */

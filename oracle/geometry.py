@@ -14,12 +14,15 @@ Follows Section II-C and Fig. 2(a) of the paper: every RWG function
 
 plus a via class (a vertical strip joining layers 0 and 1, active iff the two
 pixels it joins are on).  Each pixel carries two triangles whose diagonals
-alternate in a checkerboard, the mesh the paper selects in Section V.
-Pixels that touch only at a corner share no edge, so they are not connected
-(the over-etch reading of Section VI-A).
+alternate in a checkerboard, the mesh the paper selects in Section V; with
+``spec.sub`` = s > 1 every pixel is an s x s grid of such squares (8 or 18
+triangles per pixel, the denser meshes of the mesh study), the checkerboard
+taken over the squares.  Pixels that touch only at a corner share no edge,
+so they are not connected (the over-etch reading of Section VI-A).
 
-Vertices are identified by exact integer keys (2x, 2y, layer) in units of
-half a pixel, so topology can be checked without floating-point tolerances.
+Vertices are identified by exact integer keys in units of half a square
+side (2 s x, 2 s y, layer at pixel corners), so topology can be checked
+without floating-point tolerances.
 
 Parity: pinned by closed-form counts, by the equality of the classification
 rule's active set with the interior edges of a freshly meshed substructure,
@@ -55,7 +58,8 @@ class Structure:
 
     def xyz(self, key):
         s = self.spec
-        return np.array([key[0] * s.a / 2.0, key[1] * s.a / 2.0, -key[2] * s.h])
+        u = s.a / (2.0 * _sub(s))  # key unit: half a square side
+        return np.array([key[0] * u, key[1] * u, -key[2] * s.h])
 
     def tri_xyz(self) -> np.ndarray:
         return np.array([[self.xyz(k) for k in t] for t in self.tri_keys])
@@ -75,76 +79,128 @@ class Structure:
         return np.array([all(pm[c] for c in bf.cells) for bf in self.bfs], dtype=bool)
 
 
-def _pixel_tris(x, y, l):
-    LL, LR, UR, UL = (2 * x, 2 * y, l), (2 * x + 2, 2 * y, l), (2 * x + 2, 2 * y + 2, l), (2 * x, 2 * y + 2, l)
-    if (x + y) % 2 == 0:  # diagonal from lower-left to upper-right
+def _sub(spec) -> int:
+    """Sub-squares per pixel side: 1 (2 triangles per pixel), 2 (8), 3 (18)."""
+    return int(getattr(spec, "sub", 1) or 1)
+
+
+def _square_tris(X0, Y0, l, parity):
+    """One square of side 2 key units at (X0, Y0) split into two right
+    triangles: parity 0 along the lower-left/upper-right diagonal, 1 along
+    the lower-right/upper-left one.  Returns (lower, upper, diagonal edge);
+    the lower triangle holds the bottom side, the upper the top side."""
+    LL, LR, UR, UL = (X0, Y0, l), (X0 + 2, Y0, l), (X0 + 2, Y0 + 2, l), (X0, Y0 + 2, l)
+    if parity == 0:
         return (LL, LR, UR), (LL, UR, UL), (LL, UR)
-    return (LL, LR, UL), (LR, UR, UL), (LR, UL)  # diagonal from lower-right to upper-left
+    return (LL, LR, UL), (LR, UR, UL), (LR, UL)
 
 
-def _pixel_side_tri(x, y, side):
-    """Which of the pixel's two triangles (0 = lower, 1 = upper) holds a side."""
-    even = (x + y) % 2 == 0
+def _square_side(parity, side):
+    """Which triangle of a square (0 = lower, 1 = upper) holds a side."""
     if side == "bottom":
         return 0
     if side == "top":
         return 1
     if side == "left":
-        return 1 if even else 0
+        return 1 if parity == 0 else 0
     if side == "right":
-        return 0 if even else 1
+        return 0 if parity == 0 else 1
     raise ValueError(side)
 
 
 def _rect_tris(x0, x1, y0, y1, l):
-    """Rectangle (half-pixel key units) split by its lower-left/upper-right
-    diagonal; the lower triangle holds the bottom and right sides."""
+    """Rectangle (key units) split by its lower-left/upper-right diagonal;
+    the lower triangle holds the bottom and right sides."""
     LL, LR, UR, UL = (x0, y0, l), (x1, y0, l), (x1, y1, l), (x0, y1, l)
     return (LL, LR, UR), (LL, UR, UL), (LL, UR)
 
 
+def _centroid(tri):
+    return tuple(sum(v[i] for v in tri) / 3.0 for i in range(3))
+
+
+def _lower_first(tri_keys, t1, t2):
+    """(+, -) triangles of an in-plane edge: the lower centroid y first, the
+    smaller centroid x on a tie."""
+    c1, c2 = _centroid(tri_keys[t1]), _centroid(tri_keys[t2])
+    return (t1, t2) if (c1[1], c1[0]) < (c2[1], c2[0]) else (t2, t1)
+
+
 def build_structure(spec) -> Structure:
+    """Mesh of the parent structure: every pixel an s x s grid of squares
+    (s = spec.sub, default 1), each square split into two right triangles
+    whose diagonals alternate in a checkerboard over the squares (the
+    alternating mesh of Section V; s = 1, 2, 3 give 2, 8, 18 triangles per
+    pixel).  Vertex keys are integers in units of half a square side."""
     nx, ny, L = spec.nx, spec.ny, spec.n_layers
+    s = _sub(spec)
+    W = 2 * s  # pixel side in key units
     tri_keys, tri_owner = [], []
-    cell_tris = {}
-    for l in range(L):
-        for y in range(ny):
-            for x in range(nx):
-                lo, up, _ = _pixel_tris(x, y, l)
-                c = l * ny * nx + y * nx + x
-                cell_tris[c] = (len(tri_keys), len(tri_keys) + 1)
-                tri_keys += [lo, up]
-                tri_owner += [("cell", c), ("cell", c)]
+    sq = {}  # (cell, u, v) -> (lower, upper, parity)
 
     def cidx(l, x, y):
         return l * ny * nx + y * nx + x
 
-    def side_tri(l, x, y, side):
-        return cell_tris[cidx(l, x, y)][_pixel_side_tri(x, y, side)]
+    for l in range(L):
+        for y in range(ny):
+            for x in range(nx):
+                c = cidx(l, x, y)
+                for v in range(s):
+                    for u in range(s):
+                        par = (s * x + u + s * y + v) % 2
+                        lo, up, _ = _square_tris(W * x + 2 * u, W * y + 2 * v, l, par)
+                        sq[(c, u, v)] = (len(tri_keys), len(tri_keys) + 1, par)
+                        tri_keys += [lo, up]
+                        tri_owner += [("cell", c), ("cell", c)]
+
+    def side_tri(c, u, v, side):
+        lo, up, par = sq[(c, u, v)]
+        return (lo, up)[_square_side(par, side)]
 
     inner, inter_h, inter_v = [], [], []
     for l in range(L):
         for y in range(ny):
             for x in range(nx):
                 c = cidx(l, x, y)
-                _, _, diag = _pixel_tris(x, y, l)
-                inner.append(BasisFunction(KIND_INNER, (c,), diag, cell_tris[c][0], cell_tris[c][1]))
+                fs = []
+                for v in range(s):
+                    for u in range(s):
+                        lo, up, par = sq[(c, u, v)]
+                        fs.append(((lo, up), _square_tris(W * x + 2 * u, W * y + 2 * v, l, par)[2]))
+                        X0, Y0 = W * x + 2 * u, W * y + 2 * v
+                        if u + 1 < s:  # side between squares (u, v) and (u + 1, v)
+                            fs.append((_lower_first(tri_keys, side_tri(c, u, v, "right"),
+                                                    side_tri(c, u + 1, v, "left")),
+                                       ((X0 + 2, Y0, l), (X0 + 2, Y0 + 2, l))))
+                        if v + 1 < s:  # side between squares (u, v) and (u, v + 1)
+                            fs.append(((side_tri(c, u, v, "top"), side_tri(c, u, v + 1, "bottom")),
+                                       ((X0, Y0 + 2, l), (X0 + 2, Y0 + 2, l))))
+                # order inside the pixel: by the edge's midpoint, y first
+                fs.sort(key=lambda f: (f[1][0][1] + f[1][1][1], f[1][0][0] + f[1][1][0]))
+                for (tp, tm), e in fs:
+                    inner.append(BasisFunction(KIND_INNER, (c,), e, tp, tm))
     for l in range(L):
         for y in range(ny):
             for x in range(nx - 1):
-                e = ((2 * x + 2, 2 * y, l), (2 * x + 2, 2 * y + 2, l))
-                inter_h.append(BasisFunction(KIND_INTER, (cidx(l, x, y), cidx(l, x + 1, y)), e,
-                                             side_tri(l, x, y, "right"), side_tri(l, x + 1, y, "left")))
+                a, b = cidx(l, x, y), cidx(l, x + 1, y)
+                for v in range(s):
+                    e = ((W * (x + 1), W * y + 2 * v, l), (W * (x + 1), W * y + 2 * v + 2, l))
+                    inter_h.append(BasisFunction(KIND_INTER, (a, b), e, side_tri(a, s - 1, v, "right"),
+                                                 side_tri(b, 0, v, "left")))
     for l in range(L):
         for y in range(ny - 1):
             for x in range(nx):
-                e = ((2 * x, 2 * y + 2, l), (2 * x + 2, 2 * y + 2, l))
-                inter_v.append(BasisFunction(KIND_INTER, (cidx(l, x, y), cidx(l, x, y + 1)), e,
-                                             side_tri(l, x, y, "top"), side_tri(l, x, y + 1, "bottom")))
+                a, b = cidx(l, x, y), cidx(l, x, y + 1)
+                for u in range(s):
+                    e = ((W * x + 2 * u, W * (y + 1), l), (W * x + 2 * u + 2, W * (y + 1), l))
+                    inter_v.append(BasisFunction(KIND_INTER, (a, b), e, side_tri(a, u, s - 1, "top"),
+                                                 side_tri(b, u, 0, "bottom")))
 
-    # Feeds: a one-pixel pad beyond the middle cell of a grid side, cut into an
-    # inner and an outer half strip.  The delta-gap port sits on the line
-    # between the two half strips; + side is the outer (source) side.
+    # Feeds: a pad one square wide beyond square m = s // 2 of the middle
+    # cell's grid side (the whole pixel side when s = 1), cut into an inner
+    # and an outer half strip.  The delta-gap port sits on the line between
+    # the two half strips; + side is the outer (source) side.
+    m = s // 2
     pixport, feed_diag, port_edge = [], [], []
     for k, ps in enumerate(spec.ports):
         l = ps.layer
@@ -152,22 +208,24 @@ def build_structure(spec) -> Structure:
             j = ny // 2
             cx = nx - 1 if ps.side == "right" else 0
             cell = (cx, j)
+            ya, yb = W * j + 2 * m, W * j + 2 * m + 2
             if ps.side == "right":
-                inner_r = (2 * nx, 2 * nx + 1, 2 * j, 2 * j + 2)
-                outer_r = (2 * nx + 1, 2 * nx + 2, 2 * j, 2 * j + 2)
+                inner_r = (W * nx, W * nx + 1, ya, yb)
+                outer_r = (W * nx + 1, W * nx + 2, ya, yb)
             else:
-                inner_r = (-1, 0, 2 * j, 2 * j + 2)
-                outer_r = (-2, -1, 2 * j, 2 * j + 2)
+                inner_r = (-1, 0, ya, yb)
+                outer_r = (-2, -1, ya, yb)
         else:
             j = nx // 2
             cy = ny - 1 if ps.side == "top" else 0
             cell = (j, cy)
+            xa, xb = W * j + 2 * m, W * j + 2 * m + 2
             if ps.side == "top":
-                inner_r = (2 * j, 2 * j + 2, 2 * ny, 2 * ny + 1)
-                outer_r = (2 * j, 2 * j + 2, 2 * ny + 1, 2 * ny + 2)
+                inner_r = (xa, xb, W * ny, W * ny + 1)
+                outer_r = (xa, xb, W * ny + 1, W * ny + 2)
             else:
-                inner_r = (2 * j, 2 * j + 2, -1, 0)
-                outer_r = (2 * j, 2 * j + 2, -2, -1)
+                inner_r = (xa, xb, -1, 0)
+                outer_r = (xa, xb, -2, -1)
         ilo, iup, idiag = _rect_tris(*inner_r, l)
         olo, oup, odiag = _rect_tris(*outer_r, l)
         t0 = len(tri_keys)
@@ -175,45 +233,56 @@ def build_structure(spec) -> Structure:
         tri_owner += [("feed", k, "inner"), ("feed", k, "inner"), ("feed", k, "outer"), ("feed", k, "outer")]
         T_ilo, T_iup, T_olo, T_oup = t0, t0 + 1, t0 + 2, t0 + 3
         x0i, x1i, y0i, y1i = inner_r
+        c = cidx(l, cell[0], cell[1])
         if ps.side == "right":
             pe = ((x1i, y0i, l), (x1i, y1i, l))
             port_pair = (T_oup, T_ilo)  # outer strip's left side / inner strip's right side
             ppe = ((x0i, y0i, l), (x0i, y1i, l))
-            pp_pair = (T_iup, side_tri(l, cell[0], cell[1], "right"))
+            pp_pair = (T_iup, side_tri(c, s - 1, m, "right"))
         elif ps.side == "left":
             pe = ((x0i, y0i, l), (x0i, y1i, l))
             port_pair = (T_olo, T_iup)
             ppe = ((x1i, y0i, l), (x1i, y1i, l))
-            pp_pair = (T_ilo, side_tri(l, cell[0], cell[1], "left"))
+            pp_pair = (T_ilo, side_tri(c, 0, m, "left"))
         elif ps.side == "top":
             pe = ((x0i, y1i, l), (x1i, y1i, l))
             port_pair = (T_olo, T_iup)
             ppe = ((x0i, y0i, l), (x1i, y0i, l))
-            pp_pair = (T_ilo, side_tri(l, cell[0], cell[1], "top"))
+            pp_pair = (T_ilo, side_tri(c, m, s - 1, "top"))
         else:  # bottom
             pe = ((x0i, y0i, l), (x1i, y0i, l))
             port_pair = (T_oup, T_ilo)
             ppe = ((x0i, y1i, l), (x1i, y1i, l))
-            pp_pair = (T_iup, side_tri(l, cell[0], cell[1], "bottom"))
-        c = cidx(l, cell[0], cell[1])
+            pp_pair = (T_iup, side_tri(c, m, 0, "bottom"))
         pixport.append(BasisFunction(KIND_PIXPORT, (c,), ppe, pp_pair[0], pp_pair[1]))
         feed_diag.append(BasisFunction(KIND_ALWAYS, (), idiag, T_ilo, T_iup))
         feed_diag.append(BasisFunction(KIND_ALWAYS, (), odiag, T_olo, T_oup))
         port_edge.append(BasisFunction(KIND_ALWAYS, (), pe, port_pair[0], port_pair[1], port=k))
 
     # Vias: a vertical strip under the lower side line of cell (x, y), from
-    # layer 0 down to layer 1, split by its top-left/bottom-right diagonal.
+    # layer 0 down to layer 1, one sub-strip per square, each split by its
+    # top-left/bottom-right diagonal.  Per via: the top junctions, then the
+    # diagonals and the sides between sub-strips (by position), then the
+    # bottom junctions.
     vias = []
     for s_i, (x, y) in enumerate(spec.via_sites()):
-        TL, TR, BR, BL = (2 * x, 2 * y, 0), (2 * x + 2, 2 * y, 0), (2 * x + 2, 2 * y, 1), (2 * x, 2 * y, 1)
-        t0 = len(tri_keys)
-        tri_keys += [(TL, TR, BR), (TL, BR, BL)]
-        tri_owner += [("via", s_i), ("via", s_i)]
-        tU, tLo = t0, t0 + 1
-        cells = (cidx(0, x, y), cidx(1, x, y))
-        vias.append(BasisFunction(KIND_VIA, cells, (TL, TR), side_tri(0, x, y, "bottom"), tU))
-        vias.append(BasisFunction(KIND_VIA, cells, (TL, BR), tU, tLo))
-        vias.append(BasisFunction(KIND_VIA, cells, (BL, BR), tLo, side_tri(1, x, y, "bottom")))
+        c0, c1 = cidx(0, x, y), cidx(1, x, y)
+        top, mid, bot = [], [], []
+        prev_up = None
+        for u in range(s):
+            X0, Y = W * x + 2 * u, W * y
+            TL, TR, BR, BL = (X0, Y, 0), (X0 + 2, Y, 0), (X0 + 2, Y, 1), (X0, Y, 1)
+            t0 = len(tri_keys)
+            tri_keys += [(TL, TR, BR), (TL, BR, BL)]
+            tri_owner += [("via", s_i), ("via", s_i)]
+            tU, tLo = t0, t0 + 1
+            top.append(BasisFunction(KIND_VIA, (c0, c1), (TL, TR), side_tri(c0, u, 0, "bottom"), tU))
+            if prev_up is not None:  # the side shared with the previous sub-strip
+                mid.append(BasisFunction(KIND_VIA, (c0, c1), (TL, BL), prev_up, tLo))
+            mid.append(BasisFunction(KIND_VIA, (c0, c1), (TL, BR), tU, tLo))
+            bot.append(BasisFunction(KIND_VIA, (c0, c1), (BL, BR), tLo, side_tri(c1, u, 0, "bottom")))
+            prev_up = tU
+        vias += top + mid + bot
 
     bfs = inner + inter_h + inter_v + pixport + vias + feed_diag + port_edge
     port_bf = [i for i, b in enumerate(bfs) if b.port >= 0]
@@ -221,10 +290,14 @@ def build_structure(spec) -> Structure:
 
 
 def expected_count(spec) -> int:
-    """Closed-form parent size: per layer nx*ny inner + (nx-1)*ny + nx*(ny-1)
-    inter functions; four functions per port; three per via."""
-    per_layer = spec.nx * spec.ny + (spec.nx - 1) * spec.ny + spec.nx * (spec.ny - 1)
-    return spec.n_layers * per_layer + 4 * len(spec.ports) + 3 * spec.n_vias
+    """Closed-form parent size with s squares per pixel side: per layer
+    (3 s^2 - 2 s) inner functions per pixel (s^2 diagonals and 2 s (s - 1)
+    sides between squares) and s per side between two pixels; four
+    functions per port; 4 s - 1 per via (s top and s bottom junctions, s
+    diagonals, s - 1 sides between sub-strips)."""
+    s = _sub(spec)
+    per_layer = spec.nx * spec.ny * (3 * s * s - 2 * s) + s * ((spec.nx - 1) * spec.ny + spec.nx * (spec.ny - 1))
+    return spec.n_layers * per_layer + 4 * len(spec.ports) + (4 * s - 1) * spec.n_vias
 
 
 def fresh_submesh_edges(struct: Structure, pixel_map) -> dict:

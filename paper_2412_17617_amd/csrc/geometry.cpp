@@ -49,8 +49,15 @@ int build_problem(const pxd_geometry* g, Problem* P, std::string* err) {
     *err = "invalid geometry";
     return PXD_EINVAL;
   }
+  if (g->sub < 0 || g->sub > 8) {
+    *err = "invalid geometry: sub must be 0..8";
+    return PXD_EINVAL;
+  }
   const int nx = g->nx, ny = g->ny, L = g->n_layers;
+  const int S = g->sub > 1 ? g->sub : 1;  // squares per pixel side
+  const int W = 2 * S;                      // pixel side in key units (half a square side)
   P->g = *g;
+  P->sub = S;
   P->port_side.assign(g->port_side, g->port_side + g->n_ports);
   P->port_layer.assign(g->port_layer, g->port_layer + g->n_ports);
   P->via_x.assign(g->via_x, g->via_x + g->n_vias);
@@ -73,22 +80,29 @@ int build_problem(const pxd_geometry* g, Problem* P, std::string* err) {
 
   auto& tris = P->tris;
   tris.clear();
+  // every pixel an S x S grid of squares, each cut into two right triangles
+  // along the diagonal that alternates in a checkerboard over the squares
   for (int l = 0; l < L; ++l)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int c = (l * ny + y) * nx + x;
-        VKey LL{2 * x, 2 * y, l}, LR{2 * x + 2, 2 * y, l}, UR{2 * x + 2, 2 * y + 2, l}, UL{2 * x, 2 * y + 2, l};
-        if (((x + y) & 1) == 0) {
-          tris.push_back(Tri{{LL, LR, UR}, OWN_CELL, c, 0});
-          tris.push_back(Tri{{LL, UR, UL}, OWN_CELL, c, 1});
-        } else {
-          tris.push_back(Tri{{LL, LR, UL}, OWN_CELL, c, 0});
-          tris.push_back(Tri{{LR, UR, UL}, OWN_CELL, c, 1});
-        }
+        for (int v = 0; v < S; ++v)
+          for (int u = 0; u < S; ++u) {
+            const int X0 = W * x + 2 * u, Y0 = W * y + 2 * v;
+            VKey LL{X0, Y0, l}, LR{X0 + 2, Y0, l}, UR{X0 + 2, Y0 + 2, l}, UL{X0, Y0 + 2, l};
+            if (((S * x + u + S * y + v) & 1) == 0) {
+              tris.push_back(Tri{{LL, LR, UR}, OWN_CELL, c, 0});
+              tris.push_back(Tri{{LL, UR, UL}, OWN_CELL, c, 1});
+            } else {
+              tris.push_back(Tri{{LL, LR, UL}, OWN_CELL, c, 0});
+              tris.push_back(Tri{{LR, UR, UL}, OWN_CELL, c, 1});
+            }
+          }
       }
-  // feeds: a one-pixel pad beyond the middle cell of the side, cut in an
-  // inner and an outer half strip
+  // feeds: a pad one square wide beyond square S / 2 of the middle cell's
+  // side, cut in an inner and an outer half strip
   std::vector<int> port_cell(g->n_ports);
+  const int m = S / 2;
   for (int k = 0; k < g->n_ports; ++k) {
     int side = P->port_side[k], l = P->port_layer[k];
     int jy = ny / 2, jx = nx / 2;
@@ -97,22 +111,22 @@ int build_problem(const pxd_geometry* g, Problem* P, std::string* err) {
     switch (side) {
       case 0:  // right
         cx = nx - 1, cy = jy;
-        ix[0][0] = 2 * nx, ix[0][1] = 2 * nx + 1, ix[1][0] = 2 * nx + 1, ix[1][1] = 2 * nx + 2;
-        iy[0][0] = iy[1][0] = 2 * jy, iy[0][1] = iy[1][1] = 2 * jy + 2;
+        ix[0][0] = W * nx, ix[0][1] = W * nx + 1, ix[1][0] = W * nx + 1, ix[1][1] = W * nx + 2;
+        iy[0][0] = iy[1][0] = W * jy + 2 * m, iy[0][1] = iy[1][1] = W * jy + 2 * m + 2;
         break;
       case 2:  // left
         cx = 0, cy = jy;
         ix[0][0] = -1, ix[0][1] = 0, ix[1][0] = -2, ix[1][1] = -1;
-        iy[0][0] = iy[1][0] = 2 * jy, iy[0][1] = iy[1][1] = 2 * jy + 2;
+        iy[0][0] = iy[1][0] = W * jy + 2 * m, iy[0][1] = iy[1][1] = W * jy + 2 * m + 2;
         break;
       case 1:  // top
         cx = jx, cy = ny - 1;
-        ix[0][0] = ix[1][0] = 2 * jx, ix[0][1] = ix[1][1] = 2 * jx + 2;
-        iy[0][0] = 2 * ny, iy[0][1] = 2 * ny + 1, iy[1][0] = 2 * ny + 1, iy[1][1] = 2 * ny + 2;
+        ix[0][0] = ix[1][0] = W * jx + 2 * m, ix[0][1] = ix[1][1] = W * jx + 2 * m + 2;
+        iy[0][0] = W * ny, iy[0][1] = W * ny + 1, iy[1][0] = W * ny + 1, iy[1][1] = W * ny + 2;
         break;
       default:  // bottom
         cx = jx, cy = 0;
-        ix[0][0] = ix[1][0] = 2 * jx, ix[0][1] = ix[1][1] = 2 * jx + 2;
+        ix[0][0] = ix[1][0] = W * jx + 2 * m, ix[0][1] = ix[1][1] = W * jx + 2 * m + 2;
         iy[0][0] = -1, iy[0][1] = 0, iy[1][0] = -2, iy[1][1] = -1;
         break;
     }
@@ -120,12 +134,16 @@ int build_problem(const pxd_geometry* g, Problem* P, std::string* err) {
     add_rect(tris, ix[0][0], ix[0][1], iy[0][0], iy[0][1], l, OWN_FEED_INNER, k);
     add_rect(tris, ix[1][0], ix[1][1], iy[1][0], iy[1][1], l, OWN_FEED_OUTER, k);
   }
-  // vias: vertical strip under the lower side of cell (x, y), layers 0 -> 1
+  // vias: vertical strip under the lower side of cell (x, y), layers 0 -> 1,
+  // one sub-strip per square of that side
   for (int v = 0; v < g->n_vias; ++v) {
     int x = P->via_x[v], y = P->via_y[v];
-    VKey TL{2 * x, 2 * y, 0}, TR{2 * x + 2, 2 * y, 0}, BR{2 * x + 2, 2 * y, 1}, BL{2 * x, 2 * y, 1};
-    tris.push_back(Tri{{TL, TR, BR}, OWN_VIA, v, 1});
-    tris.push_back(Tri{{TL, BR, BL}, OWN_VIA, v, 0});
+    for (int u = 0; u < S; ++u) {
+      const int X0 = W * x + 2 * u, Y = W * y;
+      VKey TL{X0, Y, 0}, TR{X0 + 2, Y, 0}, BR{X0 + 2, Y, 1}, BL{X0, Y, 1};
+      tris.push_back(Tri{{TL, TR, BR}, OWN_VIA, v, 1});
+      tris.push_back(Tri{{TL, BR, BL}, OWN_VIA, v, 0});
+    }
   }
 
   // interior edges of the parent mesh
@@ -150,8 +168,10 @@ int build_problem(const pxd_geometry* g, Problem* P, std::string* err) {
     f.e1 = ek.b;
     f.cell_a = f.cell_b = -1;
     f.port = -1;
-    auto lower_y_first = [&](int p, int q) {
-      if (centroid_coord(tris[p], 1) < centroid_coord(tris[q], 1)) f.tp = p, f.tm = q;
+    auto lower_y_first = [&](int p, int q) {  // lower centroid y, then smaller x
+      const double yp = centroid_coord(tris[p], 1), yq = centroid_coord(tris[q], 1);
+      const bool p_first = yp < yq || (yp == yq && centroid_coord(tris[p], 0) < centroid_coord(tris[q], 0));
+      if (p_first) f.tp = p, f.tm = q;
       else f.tp = q, f.tm = p;
     };
     auto higher_z_first = [&](int p, int q) {
@@ -166,7 +186,9 @@ int build_problem(const pxd_geometry* g, Problem* P, std::string* err) {
         f.kind = PXD_KIND_INNER;
         f.cell_a = A.owner;
         lower_y_first(t1, t2);
-        f.cls = 0, f.k0 = l, f.k1 = y, f.k2 = x, f.k3 = 0;
+        // inside the pixel: by the edge's midpoint, y first
+        const int my = ek.a.y2 + ek.b.y2 - 2 * W * y, mx = ek.a.x2 + ek.b.x2 - 2 * W * x;
+        f.cls = 0, f.k0 = l, f.k1 = y, f.k2 = x, f.k3 = my * (2 * W + 1) + mx;
       } else {
         int la, xa, ya, lb, xb, yb;
         cell_xyz(A.owner, la, xa, ya);
@@ -182,7 +204,8 @@ int build_problem(const pxd_geometry* g, Problem* P, std::string* err) {
         int l, x, y;
         cell_xyz(c0, l, x, y);
         if (ya == yb) f.cls = 1; else f.cls = 2;
-        f.k0 = l, f.k1 = y, f.k2 = x, f.k3 = 0;
+        // the side's squares in order along it
+        f.k0 = l, f.k1 = y, f.k2 = x, f.k3 = (ya == yb) ? ek.a.y2 + ek.b.y2 : ek.a.x2 + ek.b.x2;
       }
     } else if ((ka == OWN_FEED_INNER || ka == OWN_FEED_OUTER) && (kb == OWN_FEED_INNER || kb == OWN_FEED_OUTER)) {
       if (A.owner != B.owner) return false;
@@ -219,7 +242,7 @@ int build_problem(const pxd_geometry* g, Problem* P, std::string* err) {
       int sub;
       if (ka == OWN_VIA && kb == OWN_VIA) sub = 1;
       else sub = (ek.a.l == 0) ? 0 : 2;  // junction on layer 0 (top) or layer 1 (bottom)
-      f.cls = 4, f.k0 = v, f.k1 = sub, f.k2 = f.k3 = 0;
+      f.cls = 4, f.k0 = v, f.k1 = sub, f.k2 = ek.a.x2 + ek.b.x2, f.k3 = 0;  // by position along the strip
     } else {
       return false;
     }

@@ -10,7 +10,8 @@
 
 namespace pxd {
 
-// Vertex in half-pixel integer units: (2x, 2y, layer).
+// Vertex in integer units of half a square side (a / (2 sub)): pixel corners
+// at (2 sub x, 2 sub y, layer).
 struct VKey {
   int x2, y2, l;
   bool operator<(const VKey& o) const {
@@ -47,9 +48,11 @@ struct Problem {
   std::vector<Rwg> rwg;
   std::vector<int> port_bf;
   int n_cells = 0;
+  int sub = 1;  // squares per pixel side
 
   std::array<double, 3> xyz(const VKey& k) const {
-    return {k.x2 * g.a * 0.5, k.y2 * g.a * 0.5, -k.l * g.h};
+    const double u = g.a / (2.0 * sub);
+    return {k.x2 * u, k.y2 * u, -k.l * g.h};
   }
 };
 

@@ -38,6 +38,7 @@ class Geometry(C.Structure):
         ("a", C.c_double), ("h", C.c_double), ("eps_r", C.c_double), ("tan_d", C.c_double),
         ("n_ports", C.c_int32), ("port_side", C.POINTER(C.c_int32)), ("port_layer", C.POINTER(C.c_int32)),
         ("n_vias", C.c_int32), ("via_x", C.POINTER(C.c_int32)), ("via_y", C.POINTER(C.c_int32)),
+        ("sub", C.c_int32),
     ]
 
 
@@ -158,7 +159,7 @@ def refine_verdict(iters, ir_max, m, m_prev, target):
 class Problem:
     """Mesh + RWG classification + host EFIE fill of one workload geometry."""
 
-    def __init__(self, n_layers, nx, ny, a, h, eps_r, tan_d, ports, vias=()):
+    def __init__(self, n_layers, nx, ny, a, h, eps_r, tan_d, ports, vias=(), sub=1):
         L = lib()
         self._keep = [
             np.array([SIDES[s] if isinstance(s, str) else int(s) for s, _ in ports] or [0], dtype=np.int32),
@@ -170,7 +171,7 @@ class Problem:
                      self._keep[0].ctypes.data_as(C.POINTER(C.c_int32)),
                      self._keep[1].ctypes.data_as(C.POINTER(C.c_int32)), len(vias),
                      self._keep[2].ctypes.data_as(C.POINTER(C.c_int32)),
-                     self._keep[3].ctypes.data_as(C.POINTER(C.c_int32)))
+                     self._keep[3].ctypes.data_as(C.POINTER(C.c_int32)), int(sub))
         h_ = _VP()
         _check(L.pxd_problem_create(C.byref(g), C.byref(h_)))
         self._h = h_
@@ -181,9 +182,10 @@ class Problem:
     @classmethod
     def from_spec(cls, spec):
         """Build from any object with the workload attributes (n_layers, nx, ny,
-        a, h, eps_r, tan_d, ports with .side/.layer, via_sites())."""
+        a, h, eps_r, tan_d, ports with .side/.layer, via_sites(), optionally
+        sub)."""
         return cls(spec.n_layers, spec.nx, spec.ny, spec.a, spec.h, spec.eps_r, spec.tan_d,
-                   [(p.side, p.layer) for p in spec.ports], list(spec.via_sites()))
+                   [(p.side, p.layer) for p in spec.ports], list(spec.via_sites()), getattr(spec, "sub", 1))
 
     def classification(self):
         kind = np.zeros(self.M, np.uint8)

@@ -48,6 +48,7 @@ class WorkloadSpec:
     n_vias: int = 0
     z0: float = 50.0
     candidates: str = "single"  # "single" or "pair3x3"
+    sub: int = 1  # squares per pixel side: 1, 2, 3 give 2, 8, 18 triangles per pixel
 
     @property
     def n_cells(self) -> int:
@@ -135,7 +136,31 @@ SPECS = {
         ports=_p(("right", 1), ("left", 2), ("left", 0)), n_freq=201, f_lo=0.5e9, f_hi=10.0e9,
         seed=5, candidates="pair3x3",
     ),
+    # The 8-triangle alternating mesh (every pixel a 2 x 2 grid of squares):
+    # two layers of 12x12 pixels in the batched20 dielectric, 6 vias, 41
+    # frequencies; and the paper-size stripline parent (two layers of 30x30
+    # pixels, 8 triangles per pixel, about 21,500 functions) whose fill is
+    # checked on sampled entries.
+    "mesh8": WorkloadSpec(
+        name="mesh8", n_layers=2, nx=12, ny=12, a=0.5e-3, h=0.5e-3, eps_r=3.5, tan_d=0.002,
+        ports=_p(("right", 0), ("top", 0), ("left", 1)), n_freq=41, f_lo=1.0e9, f_hi=8.0e9,
+        seed=6, n_vias=6, sub=2,
+    ),
+    "paper30": WorkloadSpec(
+        name="paper30", n_layers=2, nx=30, ny=30, a=0.5e-3, h=0.5e-3, eps_r=3.66, tan_d=0.004,
+        ports=_p(("right", 0), ("top", 0), ("left", 1)), n_freq=72, f_lo=1.0e9, f_hi=8.0e9,
+        seed=7, n_vias=13, sub=2,
+    ),
     # Small cases for CPU tests.
+    "tiny4x2s2": WorkloadSpec(
+        name="tiny4x2s2", n_layers=2, nx=4, ny=4, a=0.5e-3, h=0.5e-3, eps_r=3.5, tan_d=0.002,
+        ports=_p(("right", 0), ("top", 0), ("left", 1)), n_freq=4, f_lo=5.0e9, f_hi=7.0e9,
+        seed=12, n_vias=3, sub=2,
+    ),
+    "tiny3s3": WorkloadSpec(
+        name="tiny3s3", n_layers=1, nx=3, ny=3, a=1.0e-3, h=0.0, eps_r=1.0, tan_d=0.0,
+        ports=_p(("right", 0), ("left", 0)), n_freq=5, f_lo=3.5e9, f_hi=5.5e9, seed=11, sub=3,
+    ),
     "tiny3": WorkloadSpec(
         name="tiny3", n_layers=1, nx=3, ny=3, a=1.0e-3, h=0.0, eps_r=1.0, tan_d=0.0,
         ports=_p(("right", 0), ("left", 0)), n_freq=5, f_lo=3.5e9, f_hi=5.5e9, seed=11,

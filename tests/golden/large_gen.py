@@ -13,8 +13,11 @@ oracle fill of these parents takes minutes.
   large_dense24.npz   : the 24 x 24 x 3 stack with a 0.65-density map
                         (active size ~2,530, above one workgroup's 2,048):
                         6 seeded single flips at 2 frequencies.
+  large_mesh8.npz     : the 8-triangle mesh (2 layers of 12 x 12 pixels, each
+                        a 2 x 2 grid of squares; M = 3,414, active size
+                        ~1,400): 8 seeded single flips at 4 frequencies.
 
-Usage: python tests/golden/large_gen.py [ceiling32] [dense24]
+Usage: python tests/golden/large_gen.py [ceiling32] [dense24] [mesh8]
 """
 
 import dataclasses
@@ -40,6 +43,7 @@ def cases():
         # name: (spec, number of candidates, candidate seed, frequency indices)
         "ceiling32": (c32, 16, 505, [0, 63, 105, 120, 133]),
         "dense24": (d24, 6, 506, [0, 64]),
+        "mesh8": (get_spec("mesh8"), 8, 507, [0, 24, 29, 40]),
     }
 
 

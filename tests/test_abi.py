@@ -32,7 +32,8 @@ def test_every_declared_symbol_is_exported():
     assert set(syms) <= set(pxd._SIGS)
 
 
-@pytest.mark.parametrize("name", ["plain8", "tiny4x2", "small6x3", "batched20", "stress24"])
+@pytest.mark.parametrize("name", ["plain8", "tiny4x2", "small6x3", "batched20", "stress24", "tiny4x2s2", "tiny3s3",
+                                  "mesh8"])
 def test_structure_matches_oracle(name):
     spec = get_spec(name)
     pb = pxd.Problem.from_spec(spec)
@@ -46,7 +47,7 @@ def test_structure_matches_oracle(name):
     assert np.array_equal(plen, length[st.port_bf])
 
 
-@pytest.mark.parametrize("name", ["plain8", "tiny4x2", "small6x3"])
+@pytest.mark.parametrize("name", ["plain8", "tiny4x2", "small6x3", "tiny4x2s2", "tiny3s3"])
 def test_host_fill_matches_oracle_fill(name):
     """Two independent implementations of the same discretisation."""
     spec = get_spec(name)

@@ -1,0 +1,129 @@
+"""GPU parity on the denser meshes of the mesh study (GPU): every pixel an
+s x s grid of squares, each split into two right triangles with the
+diagonals alternating over the squares (s = 2: 8 triangles per pixel, s = 3:
+18), through the C ABI.
+
+* Small stacks: the library's own parent fill on the GPU against the
+  oracle's fill (1e-12 of max |Z|), and the evaluation of every flip in
+  FP64 (1e-10) and complex64 + FP64 refinement (1e-4) on both LU paths,
+  against the oracle's fill, Eq. 5 gather, LAPACK solve and Eqs. 6-7.
+* The 12 x 12 x 2 stack with 8 triangles per pixel (M = 3,414): sampled
+  oracle references from tests/golden/large_gen.py.
+* The paper-size parent (2 layers of 30 x 30 pixels, 8 triangles per pixel,
+  M = 21,463): the GPU fill of one frequency against the oracle's fill of a
+  seeded 160-function principal submatrix; its active sizes (~9,000) are
+  beyond the tiled LU's 4,096 and are refused.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import efie, geometry, search
+from paper_2412_17617_amd import pxd
+from synth import get_spec, permutation
+
+from gpu_common import make_evaluator, oracle_parent
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+S_TOL = {pxd.PREC_FP64: 1e-10, pxd.PREC_MIXED32: 1e-4}
+
+
+def device_fill(pb, freqs):
+    out = torch.empty((len(freqs), pb.M, pb.M), dtype=torch.complex128, device="cuda:0")
+    pb.fill_device(freqs, out)
+    return out
+
+
+@pytest.mark.parametrize("name", ["tiny4x2s2", "tiny3s3"])
+def test_subdivided_fill_and_evaluation_match_oracle(name):
+    spec = get_spec(name)
+    st, Zo, freqs = oracle_parent(spec)
+    pb = pxd.Problem.from_spec(spec)
+    Z = device_fill(pb, freqs).cpu().numpy()
+    err = np.abs(Z - Zo).max() / np.abs(Zo).max()
+    print(f"{name}: M {pb.M}, GPU fill max |dZ| / max |Z| = {err:.2e}", flush=True)
+    assert np.array_equal(Z, np.transpose(Z, (0, 2, 1)))
+    assert err <= 1e-12
+    base = spec.base_map()
+    off, cells = spec.flips()
+    S_o, F_o = search.sweep(st, Zo, base, off, cells, freqs)
+    for prec in (pxd.PREC_FP64, pxd.PREC_MIXED32):
+        for path in (pxd.PATH_PERSISTENT, pxd.PATH_TILED):
+            ev, _ = make_evaluator(spec, Zo, freqs, precision=prec, lu_path=path)
+            S, F, status, am = ev.evaluate_flips(base, off, cells)
+            stats = ev.stats()
+            ev.close()
+            dS = np.abs(S - S_o).max()
+            print(f"  precision {prec} path {path}: N {stats['min_active']}-{stats['max_active']}, "
+                  f"max |dS| {dS:.2e}", flush=True)
+            assert np.all((status == pxd.STATUS_OK) | (status == pxd.STATUS_FALLBACK))
+            assert dS <= S_TOL[prec]
+            assert np.all(np.abs(F - F_o) <= 1e-6 * F_o)
+
+
+def test_mesh8_sampled_against_oracle():
+    spec = get_spec("mesh8")
+    ref = np.load(os.path.join(GOLD, "large_mesh8.npz"))
+    fidx = ref["fidx"]
+    freqs = spec.freqs[fidx]
+    pb = pxd.Problem.from_spec(spec)
+    base = spec.base_map()
+    off, cells = spec.flips()
+    pick = ref["pick"]
+    sub_off = np.zeros(len(pick) + 1, np.int32)
+    sub_off[1:] = np.cumsum([off[c + 1] - off[c] for c in pick])
+    sub_cells = np.concatenate([cells[off[c]:off[c + 1]] for c in pick]).astype(np.int32)
+    for prec in (pxd.PREC_FP64, pxd.PREC_MIXED32):
+        for path in (pxd.PATH_PERSISTENT, pxd.PATH_TILED):
+            ev = pxd.Evaluator(precision=prec, lu_path=path)
+            ev.load_problem(pb, spec.z0)
+            ev.load_parent_problem(pb, freqs)
+            ev.set_fom_paper()
+            S, F, status, am = ev.evaluate_flips(base, sub_off, sub_cells)
+            stats = ev.stats()
+            ev.close()
+            dS = np.abs(S - ref["S"]).max()
+            print(f"mesh8 precision {prec} path {path}: N {stats['min_active']}-{stats['max_active']} "
+                  f"(oracle {ref['N'].min()}-{ref['N'].max()}), max |dS| {dS:.2e}", flush=True)
+            assert stats["min_active"] == ref["N"].min() and stats["max_active"] == ref["N"].max()
+            assert np.all((status == pxd.STATUS_OK) | (status == pxd.STATUS_FALLBACK))
+            assert dS <= (1e-8 if prec == pxd.PREC_FP64 else 1e-4)
+
+
+def test_paper_size_parent_fill_sampled():
+    spec = get_spec("paper30")
+    pb = pxd.Problem.from_spec(spec)
+    st = geometry.build_structure(spec)
+    assert pb.M == st.M == geometry.expected_count(spec) == 21463
+    fi = int(np.argmin(np.abs(spec.freqs - 5.5e9)))
+    f = spec.freqs[fi:fi + 1]
+    Zd = device_fill(pb, f)[0]
+    idx = np.sort(permutation(pb.M, 31)[:160])
+    t_idx = torch.from_numpy(idx).to("cuda:0")
+    Z = Zd[t_idx][:, t_idx].cpu().numpy()
+    scale = float(Zd.abs().max().item())
+    del Zd
+    torch.cuda.empty_cache()
+    Zo = efie.fill(st, f[0], bf_subset=idx)
+    err = np.abs(Z - Zo).max() / scale
+    print(f"paper30: M {pb.M}, sampled 160 x 160 block, max |dZ| / max |Z| = {err:.2e}", flush=True)
+    assert err <= 1e-12
+    assert np.array_equal(Z, Z.T)
+    # its candidates are beyond the LU's size limit: refused, not truncated
+    ev = pxd.Evaluator(precision=pxd.PREC_FP64)
+    ev.load_problem(pb, spec.z0)
+    ev.load_parent_problem(pb, f)
+    ev.set_fom_paper()
+    off, cells = spec.flips()
+    with pytest.raises(pxd.PxdError) as e:
+        ev.evaluate_flips(spec.base_map(), off[:3], cells[:off[2]])
+    assert e.value.code == pxd.ESHAPE
+    N, _ = ev.expand(spec.base_map(), off[:3], cells[:off[2]])
+    print(f"paper30: active sizes {N.min()}-{N.max()} refused ({e.value})", flush=True)
+    assert N.max() > 4096
+    ev.close()
