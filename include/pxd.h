@@ -178,7 +178,9 @@ typedef struct pxd_options {
  * lock step, one launch per step of each block column with many workgroups
  * per item (a panel kernel per item, then the interchanges and U12 solve and
  * the trailing-matrix update tiled over the item's columns / output tiles);
- * active sizes up to 4,096; not available in graphs or the no-allocation
+ * active sizes up to 10,240 in FP64 and up to 5,696 (P = 3) in the mixed
+ * modes, whose solves keep the right-hand sides in LDS; not available in
+ * graphs or the no-allocation
  * entry point. */
 #define PXD_PATH_AUTO 0       /* tuned value for the size class, else persistent up to 2,048 and tiled above */
 #define PXD_PATH_PERSISTENT 1

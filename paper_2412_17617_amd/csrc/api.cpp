@@ -547,6 +547,11 @@ int evaluate(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const uint8_t* d_base, si
                                    "no-allocation entry point");
     if (nmax > pxd::tl_max_active())
       return ctx->fail(PXD_ESHAPE, "active size above " + std::to_string(pxd::tl_max_active()) + " is not supported");
+    if (ctx->opt.precision != PXD_PREC_FP64 && nmax > pxd::tl_max_active_mixed(ctx->P))
+      return ctx->fail(PXD_ESHAPE, "active size above " + std::to_string(pxd::tl_max_active_mixed(ctx->P)) +
+                                       " is not supported in the mixed-precision modes (their solves keep the "
+                                       "right-hand sides in LDS); FP64 takes up to " +
+                                       std::to_string(pxd::tl_max_active()));
     if (events) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
     return evaluate_tiled(ctx, b, s, C, Nc, Ilist, cnt, item_status, fb_list, d_S, d_fom, d_cand_status, d_argmin,
                           nmin, nmax);

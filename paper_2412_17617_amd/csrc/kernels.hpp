@@ -213,7 +213,8 @@ hipError_t tl_trsm(hipStream_t s, const TlParams& p, int K, int nmax);
 hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax, int cb, int ce);
 hipError_t tl_finish(hipStream_t s, const TlParams& p, int nmax);
 hipError_t tl_prepare(const TlParams& p, int nmax);  // kernel attributes (outside capture)
-int tl_max_active();                                 // largest active size the tiled path takes
+int tl_max_active();                                 // largest active size the tiled path takes (FP64)
+int tl_max_active_mixed(int P);                      // the same for the complex64 + refinement modes
 
 // Lock-step refinement of a mixed-mode chunk.  U is the union of the batch's
 // active sets (ascending parent indices).  The chunk's items are grouped by

@@ -896,6 +896,9 @@ hipError_t panel_variant(hipStream_t s, const TlParams& p, int K, int q) {
   else if (q <= 8) hipLaunchKernelGGL((k_tl_panel<R, 8, tl_sb<R, 8>()>), g, blk, 0, s, p, K);
   else if (q <= 12) hipLaunchKernelGGL((k_tl_panel<R, 12, tl_sb<R, 12>()>), g, blk, 0, s, p, K);
   else if (q <= 16) hipLaunchKernelGGL((k_tl_panel<R, 16, tl_sb<R, 16>()>), g, blk, 0, s, p, K);
+  else if (q <= 24) hipLaunchKernelGGL((k_tl_panel<R, 24, 1>), g, blk, 0, s, p, K);
+  else if (q <= 32) hipLaunchKernelGGL((k_tl_panel<R, 32, 1>), g, blk, 0, s, p, K);
+  else if (q <= 40) hipLaunchKernelGGL((k_tl_panel<R, 40, 1>), g, blk, 0, s, p, K);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -931,7 +934,15 @@ struct UpdShape<double> {
 };
 }  // namespace
 
-int tl_max_active() { return 256 * 16; }
+int tl_max_active() { return 256 * 40; }
+
+int tl_max_active_mixed(int P) {
+  // the complex64 solves keep the item's active list and its right-hand sides
+  // in LDS (eval_mixed_lds), next to the refinement's static LDS
+  int n = tl_max_active();
+  while (n > 0 && eval_mixed_lds(n, P) + 4096 > 160 * 1024) n -= 64;
+  return n;
+}
 
 hipError_t tl_gather(hipStream_t s, const TlParams& p, int nmax) {
   const dim3 g((nmax + 15) / 16, p.B), blk(kThreads);

@@ -13,11 +13,15 @@ oracle fill of these parents takes minutes.
   large_dense24.npz   : the 24 x 24 x 3 stack with a 0.65-density map
                         (active size ~2,530, above one workgroup's 2,048):
                         6 seeded single flips at 2 frequencies.
+  large_paper30.npz   : the paper-size 8-triangle parent (2 layers of 30 x
+                        30 pixels, M = 21,463): 2 seeded single flips at
+                        5.5 GHz (active size ~9,460; the oracle fills the
+                        union of their active sets only).
   large_mesh8.npz     : the 8-triangle mesh (2 layers of 12 x 12 pixels, each
                         a 2 x 2 grid of squares; M = 3,414, active size
                         ~1,400): 8 seeded single flips at 4 frequencies.
 
-Usage: python tests/golden/large_gen.py [ceiling32] [dense24] [mesh8]
+Usage: python tests/golden/large_gen.py [ceiling32] [dense24] [mesh8] [paper30]
 """
 
 import dataclasses
@@ -44,6 +48,7 @@ def cases():
         "ceiling32": (c32, 16, 505, [0, 63, 105, 120, 133]),
         "dense24": (d24, 6, 506, [0, 64]),
         "mesh8": (get_spec("mesh8"), 8, 507, [0, 24, 29, 40]),
+        "paper30": (get_spec("paper30"), 2, 508, [47]),
     }
 
 
@@ -59,16 +64,24 @@ def run(name):
     P = len(st.port_bf)
     S = np.zeros((n_pick, len(fidx), P, P), np.complex128)
     N = np.zeros(n_pick, np.int32)
+    # large parents: the oracle fills only the union of the sampled candidates' active sets
+    union = np.zeros(st.M, bool)
+    for c in pick:
+        union |= st.active(maps[c])
+    idx = network.support(union) if st.M > 12000 else np.arange(st.M)
+    pos = -np.ones(st.M, np.int64)
+    pos[idx] = np.arange(len(idx))
     for k, fi in enumerate(fidx):
         t = time.time()
-        Z = efie.fill(st, spec.freqs[fi])
-        print(f"{name}: fill {k + 1}/{len(fidx)} ({spec.freqs[fi] / 1e9:.4f} GHz, M = {st.M}) "
-              f"{time.time() - t:.0f} s", flush=True)
+        Z = efie.fill(st, spec.freqs[fi], bf_subset=idx if len(idx) < st.M else None)
+        print(f"{name}: fill {k + 1}/{len(fidx)} ({spec.freqs[fi] / 1e9:.4f} GHz, M = {st.M}, "
+              f"{len(idx)} functions filled) {time.time() - t:.0f} s", flush=True)
         for i, c in enumerate(pick):
             sel = st.active(maps[c])
             N[i] = int(sel.sum())
-            S[i, k] = network.s_parameters(network.reduce_matrix(Z, sel), network.port_positions(sel, st.port_bf),
-                                           pl, spec.z0)
+            rows = pos[network.support(sel)]
+            S[i, k] = network.s_parameters(Z[np.ix_(rows, rows)], network.port_positions(sel, st.port_bf), pl,
+                                           spec.z0)
         del Z
     np.savez(os.path.join(HERE, f"large_{name}.npz"), pick=pick, fidx=np.asarray(fidx, np.int32), S=S, N=N,
              density=np.float64(spec.density))

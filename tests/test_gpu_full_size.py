@@ -71,11 +71,13 @@ def test_stress24_full_batch_every_precision():
 
 
 def test_active_size_above_the_tiled_limit_is_refused():
-    """The all-metal 32x32x3 map has N = M = 9,036, above the tiled LU's
-    4,096: the library refuses the batch instead of running it."""
+    """The all-metal 32x32x3 map has N = M = 9,036, above the mixed modes'
+    5,696 (their solves keep the right-hand sides in LDS): the library
+    refuses the batch instead of running it.  (The FP64 limit, 10,240, is
+    checked on the paper-size parent in test_gpu_mesh.py.)"""
     spec = get_spec("ceiling32")
     pb = pxd.Problem.from_spec(spec)
-    ev = pxd.Evaluator()
+    ev = pxd.Evaluator(precision=pxd.PREC_MIXED32)
     Z = np.zeros((1, pb.M, pb.M), np.complex128)
     ev.load_parent(Z, spec.freqs[:1])
     ev.load_problem(pb, spec.z0)

@@ -11,8 +11,8 @@ diagonals alternating over the squares (s = 2: 8 triangles per pixel, s = 3:
   oracle references from tests/golden/large_gen.py.
 * The paper-size parent (2 layers of 30 x 30 pixels, 8 triangles per pixel,
   M = 21,463): the GPU fill of one frequency against the oracle's fill of a
-  seeded 160-function principal submatrix; its active sizes (~9,000) are
-  beyond the tiled LU's 4,096 and are refused.
+  seeded 160-function principal submatrix, and two single flips (active
+  sizes ~9,460) solved in FP64 on the tiled LU against the oracle's solves.
 """
 
 import os
@@ -114,16 +114,44 @@ def test_paper_size_parent_fill_sampled():
     print(f"paper30: M {pb.M}, sampled 160 x 160 block, max |dZ| / max |Z| = {err:.2e}", flush=True)
     assert err <= 1e-12
     assert np.array_equal(Z, Z.T)
-    # its candidates are beyond the LU's size limit: refused, not truncated
-    ev = pxd.Evaluator(precision=pxd.PREC_FP64)
-    ev.load_problem(pb, spec.z0)
-    ev.load_parent_problem(pb, f)
-    ev.set_fom_paper()
+
+
+def test_paper_size_candidates_against_oracle():
+    """Two seeded single flips of the paper-size parent (active sizes ~9,460)
+    in FP64 on the tiled LU, against the oracle's solves
+    (tests/golden/large_paper30.npz); the mixed modes and the all-metal map
+    (21,463) are beyond their limits and refused."""
+    spec = get_spec("paper30")
+    ref = np.load(os.path.join(GOLD, "large_paper30.npz"))
+    freqs = spec.freqs[ref["fidx"]]
+    pb = pxd.Problem.from_spec(spec)
+    base = spec.base_map()
     off, cells = spec.flips()
-    with pytest.raises(pxd.PxdError) as e:
-        ev.evaluate_flips(spec.base_map(), off[:3], cells[:off[2]])
+    pick = ref["pick"]
+    sub_off = np.zeros(len(pick) + 1, np.int32)
+    sub_off[1:] = np.cumsum([off[c + 1] - off[c] for c in pick])
+    sub_cells = np.concatenate([cells[off[c]:off[c + 1]] for c in pick]).astype(np.int32)
+    ev = pxd.Evaluator(precision=pxd.PREC_FP64, lu_path=pxd.PATH_TILED)
+    ev.load_problem(pb, spec.z0)
+    ev.load_parent_problem(pb, freqs)
+    ev.set_fom_paper()
+    S, F, status, am = ev.evaluate_flips(base, sub_off, sub_cells)
+    stats = ev.stats()
+    dS = np.abs(S - ref["S"]).max()
+    print(f"paper30 FP64: N {stats['min_active']}-{stats['max_active']} (oracle {ref['N'].min()}-{ref['N'].max()}), "
+          f"max |dS| {dS:.2e}, {stats['ms_solve']:.0f} ms", flush=True)
+    assert stats["min_active"] == ref["N"].min() and stats["max_active"] == ref["N"].max()
+    assert np.all(status == pxd.STATUS_OK)
+    assert dS <= 1e-8
+    with pytest.raises(pxd.PxdError) as e:  # the whole parent: 21,463 > 10,240
+        ev.evaluate_flips(np.ones(spec.n_cells, np.uint8), np.array([0, 0], np.int32), np.zeros(0, np.int32))
     assert e.value.code == pxd.ESHAPE
-    N, _ = ev.expand(spec.base_map(), off[:3], cells[:off[2]])
-    print(f"paper30: active sizes {N.min()}-{N.max()} refused ({e.value})", flush=True)
-    assert N.max() > 4096
+    ev.close()
+    ev = pxd.Evaluator(precision=pxd.PREC_MIXED32, lu_path=pxd.PATH_TILED)
+    ev.load_problem(pb, spec.z0)
+    ev.load_parent_problem(pb, freqs)
+    ev.set_fom_paper()
+    with pytest.raises(pxd.PxdError) as e:  # 9,460 > the mixed modes' 5,696
+        ev.evaluate_flips(base, sub_off, sub_cells)
+    assert e.value.code == pxd.ESHAPE
     ev.close()
