@@ -884,7 +884,12 @@ __global__ void k_zero_c128(double2* __restrict__ p, size_t n) {
 
 template <typename R, int Q>
 constexpr int tl_sb() {
-  return sizeof(R) == 8 ? (16 / Q > 0 ? 16 / Q : 1) : (32 / Q > 0 ? 32 / Q : 1);
+  // register sub-panel width: Q x SB entries per thread; measured on the 24x24x3,
+  // 20x20x2 and 32x32x3 stacks, wider sub-panels pay for FP64 at every Q
+  // and for complex64 from 12 rows per thread on (fewer passes over the panel
+  // outweigh the lower occupancy there)
+  constexpr int w = sizeof(R) == 8 ? 32 / Q : (Q >= 12 ? 64 / Q : 32 / Q);
+  return w < 1 ? 1 : (w > 16 && sizeof(R) == 8 ? 16 : (w > 32 ? 32 : w));
 }
 
 template <typename R>
