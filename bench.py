@@ -546,6 +546,7 @@ def surrogate_leg(args, pxd, spec, torch):
     n = L * ny * nx
     sur = pxd.Surrogate(L, ny, nx, spec.freqs, spec.freqs[0], spec.freqs[-1], precision=pxd.SUR_BF16, max_batch=2048)
     sur.init_params(17)
+    path = {pxd.SUR_INFER_FUSED: "fused", pxd.SUR_INFER_GENERIC: "generic"}[sur.inference]
     iu, ju = np.triu_indices(n, 1)
     C = n + len(iu)
     off = np.concatenate([np.arange(n + 1), n + 2 * np.arange(1, len(iu) + 1)]).astype(np.int32)
@@ -564,6 +565,23 @@ def surrogate_leg(args, pxd, spec, torch):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     ok = bool(torch.isfinite(fp).all().item()) and int(top.min().item()) >= 0
+    generic = None
+    if sur.inference == pxd.SUR_INFER_FUSED:
+        # the same ranking through the training path's products, for comparison
+        gen = pxd.Surrogate(L, ny, nx, spec.freqs, spec.freqs[0], spec.freqs[-1], precision=pxd.SUR_BF16,
+                            max_batch=2048, inference=pxd.SUR_INFER_GENERIC)
+        gen.init_params(17)
+        fp_g = torch.empty_like(fp)
+        top_g = torch.empty_like(top)
+        gen.rank(ev, t_base, t_off, t_cells, 32, fp_g, top_g, stream)
+        e0.record(stream)
+        gen.rank(ev, t_base, t_off, t_cells, 32, fp_g, top_g, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dev_rel = float(((fp - fp_g).abs() / fp_g.abs()).max().item())
+        same_top = int(np.intersect1d(top.cpu().numpy(), top_g.cpu().numpy()).size)
+        generic = {"ms": e0.elapsed_time(e1), "max_rel_fom_dev": dev_rel, "top32_overlap": same_top}
+        gen.close()
     ch = (L, 32, 32, 64, 64)
     px = (ny * nx, ny * nx, ny * nx // 4, ny * nx // 4)
     trunk = sum(2 * 9 * ch[i] * ch[i + 1] * px[i] for i in range(4))
@@ -571,12 +589,13 @@ def surrogate_leg(args, pxd, spec, torch):
     flops = C * (trunk + 2 * feat * 256 + spec.n_freq * 2 * 256 * 9)
     sur.close()
     ev.close()
-    log(f"[surrogate] ranked {C:,} candidates in {ms:.0f} ms ({flops / (ms / 1e3) / 1e12:.1f} TFLOP/s)")
+    log(f"[surrogate] ranked {C:,} candidates in {ms:.0f} ms ({flops / (ms / 1e3) / 1e12:.1f} TFLOP/s, {path}"
+        + (f"; generic products {generic['ms']:.0f} ms)" if generic else ")"))
     return {"value": C / (ms / 1e3), "unit": "maps/s", "ms": ms, "candidates": C,
             "workload": f"every single flip and cell pair of a {L}x{ny}x{nx} map, {spec.n_freq} frequencies, top 32",
             "precision": "bf16 products, fp32 accumulation", "weights": "random init (throughput only)",
             "flops_per_call": flops, "achieved_TFLOPs": flops / (ms / 1e3) / 1e12, "peak_TFLOPs": 2500.0,
-            "top_valid": ok}
+            "top_valid": ok, "inference": path, "generic_products": generic}
 
 
 def main():

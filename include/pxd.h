@@ -424,6 +424,17 @@ void pxd_graph_destroy(pxd_graph* g);
 #define PXD_SUR_FP32 0
 #define PXD_SUR_BF16 1
 
+/* Inference path of pxd_sur_forward and pxd_sur_rank (training always uses
+ * the generic products).  FUSED: the four convolutions of one map run in one
+ * workgroup with BF16 activations held in LDS, and the head's output layer
+ * forms its hidden activations in registers; BF16 only, ny and nx multiples
+ * of 8, n_layers <= 8, channels each 16, 32 or 64, hidden a power of two
+ * >= 32.  Same operand rounding as the generic BF16 products, FP32 sums in
+ * another order.  AUTO takes FUSED where it applies, else GENERIC. */
+#define PXD_SUR_INFER_AUTO 0
+#define PXD_SUR_INFER_GENERIC 1
+#define PXD_SUR_INFER_FUSED 2
+
 typedef struct pxd_sur_config {
   int32_t device;
   int32_t n_layers, ny, nx;  /* map shape */
@@ -433,6 +444,7 @@ typedef struct pxd_sur_config {
   int32_t entry_i[4], entry_j[4];
   int32_t precision;         /* PXD_SUR_* */
   int32_t max_batch;         /* largest number of maps per call */
+  int32_t inference;         /* PXD_SUR_INFER_*; FUSED where it does not apply gives PXD_EINVAL */
 } pxd_sur_config;
 
 typedef struct pxd_adamw {
@@ -447,6 +459,8 @@ int pxd_sur_create(const pxd_sur_config* cfg, int32_t F, const double* freqs_hz,
 void pxd_sur_destroy(pxd_sur* s);
 const char* pxd_sur_last_error(const pxd_sur* s);
 int pxd_sur_num_params(const pxd_sur* s, int64_t* n);
+/* The inference path in use: PXD_SUR_INFER_GENERIC or PXD_SUR_INFER_FUSED. */
+int pxd_sur_inference_path(const pxd_sur* s, int32_t* path);
 /* Uniform initialisation from SplitMix64(seed * 1000 + tensor index): weights
  * in +-sqrt(3 / fan_in) (fan_in = product of all but the last dimension),
  * biases in +-0.05.  Resets the optimiser state. */

@@ -17,6 +17,7 @@
 
 #include "pxd.h"
 #include "status.hpp"
+#include "sur_infer.hpp"
 #include "surrogate.hpp"
 
 namespace pxd {
@@ -444,19 +445,26 @@ __global__ void k_pred_fom(const float* pred, int n, int F, int n_ent, const int
   if (lane == 0) fom[r] = acc;
 }
 
-// k smallest (value, index) pairs in increasing order; pass j takes the least
-// pair above the one pass j - 1 took, so no scratch is needed.  NaN counts as +inf.
-__global__ void k_topk(const double* v, int n, int k, int* top) {
+// k smallest (value, id) pairs in increasing order; pass j takes the least
+// pair above the one pass j - 1 took, so no scratch is needed.  NaN counts as
+// +inf.  Block g takes positions [g per, (g + 1) per) of v; ids are idx[pos]
+// (or pos when idx is null).  Writes out_v[g k + j] and out_i[g k + j]
+// (INT_MAX where fewer than k pairs exist).  One block over all of v gives
+// the top k; blocks over slices, then one block over their k each, give the
+// same k (every pair of the top k is in the top k of its slice).
+__global__ void k_topk(const double* v, const int* idx, int n, int k, int per, double* out_v, int* out_i) {
   __shared__ double sv[1024];
   __shared__ int si[1024];
+  const int lo = blockIdx.x * per, hi = min(n, lo + per);
   double pv = -__builtin_inf();
   int pi = -1;
   for (int j = 0; j < k; ++j) {
     double best = __builtin_inf();
     int bi = 0x7fffffff;
-    for (int i = threadIdx.x; i < n; i += 1024) {
-      double x = v[i];
+    for (int p = lo + (int)threadIdx.x; p < hi; p += 1024) {
+      double x = v[p];
       if (x != x) x = __builtin_inf();
+      const int i = idx ? idx[p] : p;
       const bool above = (x > pv) || (x == pv && i > pi);
       if (above && (x < best || (x == best && i < bi))) best = x, bi = i;
     }
@@ -474,9 +482,18 @@ __global__ void k_topk(const double* v, int n, int k, int* top) {
     }
     pv = sv[0];
     pi = si[0];
-    if (threadIdx.x == 0) top[j] = (pi == 0x7fffffff) ? -1 : pi;
+    if (threadIdx.x == 0) {
+      if (out_v) out_v[(size_t)blockIdx.x * k + j] = pv;
+      out_i[(size_t)blockIdx.x * k + j] = pi;
+    }
     __syncthreads();
   }
+}
+
+// INT_MAX (fewer than k candidates) -> -1
+__global__ void k_topk_ids(int k, int* top) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k && top[j] == 0x7fffffff) top[j] = -1;
 }
 
 inline dim3 grid1(size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)); }
@@ -540,12 +557,15 @@ struct pxd_sur {
   std::string err;
   int F = 0, n_out = 0, ch[5] = {}, H[3] = {}, W[3] = {}, feat = 0;
   bool bf16 = false;
+  pxd::sur::InferPlan plan;  // fused inference layout (plan.ok: in use)
+  Buf frag;                  // its packed BF16 weight fragments
   Tensor t[13];  // W1 b1 W2 b2 W3 b3 W4 b4 Wf We bh Wo bo
   size_t n_params = 0;
   long step = 0;
   Buf params, grad, m, v, u, e, ent;
   // activations and their gradients, sized for max_batch
   Buf z[4], act[4], dz, da, U, V, zh, h, out, dout, dh, dU, dV, part, maps, pred, loss;
+  Buf tk_v, tk_i;  // per-slice top-k candidates of the ranking
 
   int fail(int rc, const std::string& msg) {
     err = msg;
@@ -602,6 +622,33 @@ int forward(pxd_sur* s, hipStream_t st, int B, const uint8_t* maps) {
   Dense po{B * F, s->n_out, Hd, s->h.as<float>(), P(s, 11), Hd, s->n_out, false, false, s->out.as<float>(), P(s, 12),
            nullptr};
   SURCHK(s, gemm(st, po, s->bf16));
+  return PXD_OK;
+}
+
+// Packs the current weights into the fused kernels' fragments.
+int pack_fused(pxd_sur* s, hipStream_t st) {
+  const float* w[4] = {P(s, 0), P(s, 2), P(s, 4), P(s, 6)};
+  SURCHK(s, infer_pack(st, s->plan, w, P(s, 8), P(s, 11), s->frag.p));
+  return PXD_OK;
+}
+
+// V = e We (the frequency half of the head's first layer).
+int head_v(pxd_sur* s, hipStream_t st) {
+  Dense pv{s->F, s->cfg.hidden, s->cfg.emb, s->e.as<float>(), P(s, 9), s->cfg.emb, s->cfg.hidden, false, false,
+           s->V.as<float>(), nullptr, nullptr};
+  SURCHK(s, gemm(st, pv, s->bf16));
+  return PXD_OK;
+}
+
+// Fused forward of B maps (weights packed and V formed beforehand): trunk ->
+// act[3] (BF16), U = act[3] Wf, out = relu((U + V) + bh) Wo + bo.
+int forward_fused(pxd_sur* s, hipStream_t st, int B, const uint8_t* maps) {
+  const float* bias[4] = {P(s, 1), P(s, 3), P(s, 5), P(s, 7)};
+  SURCHK(s, infer_trunk(st, s->plan, B, maps, s->cfg.n_layers * s->cfg.ny * s->cfg.nx, s->frag.p, bias,
+                        s->act[3].p));  // BF16 here
+  SURCHK(s, infer_u(st, s->plan, B, s->act[3].p, s->frag.p, s->U.as<float>()));
+  SURCHK(s, infer_head(st, s->plan, B, s->F, s->U.as<float>(), s->V.as<float>(), P(s, 10), s->frag.p, P(s, 12),
+                       s->out.as<float>()));
   return PXD_OK;
 }
 
@@ -719,8 +766,13 @@ int pxd_sur_create(const pxd_sur_config* cfg, int32_t F, const double* freqs_hz,
   *out = nullptr;
   const pxd_sur_config& c = *cfg;
   if (c.n_layers < 1 || c.ny < 4 || c.nx < 4 || c.hidden < 1 || c.emb < 2 || (c.emb & 1) || c.n_entries < 1 ||
-      c.n_entries > 4 || c.max_batch < 1 || (c.precision != PXD_SUR_FP32 && c.precision != PXD_SUR_BF16))
+      c.n_entries > 4 || c.max_batch < 1 || (c.precision != PXD_SUR_FP32 && c.precision != PXD_SUR_BF16) ||
+      c.inference < PXD_SUR_INFER_AUTO || c.inference > PXD_SUR_INFER_FUSED)
     return pxd::set_thread_error(PXD_EINVAL, "invalid surrogate configuration");
+  if (c.inference == PXD_SUR_INFER_FUSED &&
+      (c.precision != PXD_SUR_BF16 || !pxd::sur::infer_plan(c.n_layers, c.ny, c.nx, c.channels, c.hidden,
+                                                            3 * c.n_entries).ok))
+    return pxd::set_thread_error(PXD_EINVAL, "fused inference does not cover this configuration");
   for (int i = 0; i < 4; ++i)
     if (c.channels[i] < 1 || c.channels[i] > 256) return pxd::set_thread_error(PXD_EINVAL, "channel count outside [1, 256]");
   for (int k = 0; k < c.n_entries; ++k)
@@ -784,6 +836,12 @@ int pxd_sur_create(const pxd_sur_config* cfg, int32_t F, const double* freqs_hz,
   ok(s->maps.ensure(B * c.n_layers * c.ny * c.nx));
   ok(s->pred.ensure(4 * B * F * s->n_out));
   ok(s->loss.ensure(4));
+  if (s->bf16 && c.inference != PXD_SUR_INFER_GENERIC)
+    s->plan = pxd::sur::infer_plan(c.n_layers, c.ny, c.nx, c.channels, c.hidden, s->n_out);
+  if (s->plan.ok) {
+    ok(s->frag.ensure(16 * 64 * (size_t)s->plan.n_frag));
+    ok(pxd::sur::infer_prepare(s->plan));
+  }
   if (e == hipSuccess) e = hipMemcpy(s->u.p, u.data(), 8 * F, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->ent.p, ent.data(), 4 * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
@@ -810,7 +868,8 @@ void pxd_sur_destroy(pxd_sur* s) {
   (void)hipSetDevice(s->cfg.device);
   (void)hipDeviceSynchronize();
   for (Buf* b : {&s->params, &s->grad, &s->m, &s->v, &s->u, &s->e, &s->ent, &s->dz, &s->da, &s->U, &s->V, &s->zh,
-                 &s->h, &s->out, &s->dout, &s->dh, &s->dU, &s->dV, &s->part, &s->maps, &s->pred, &s->loss})
+                 &s->h, &s->out, &s->dout, &s->dh, &s->dU, &s->dV, &s->part, &s->maps, &s->pred, &s->loss, &s->frag,
+                 &s->tk_v, &s->tk_i})
     b->release();
   for (int l = 0; l < 4; ++l) {
     s->z[l].release();
@@ -824,6 +883,12 @@ const char* pxd_sur_last_error(const pxd_sur* s) { return s ? s->err.c_str() : p
 int pxd_sur_num_params(const pxd_sur* s, int64_t* n) {
   if (!s || !n) return pxd::set_thread_error(PXD_EINVAL, "null argument");
   *n = (int64_t)s->n_params;
+  return PXD_OK;
+}
+
+int pxd_sur_inference_path(const pxd_sur* s, int32_t* path) {
+  if (!s || !path) return pxd::set_thread_error(PXD_EINVAL, "null argument");
+  *path = s->plan.ok ? PXD_SUR_INFER_FUSED : PXD_SUR_INFER_GENERIC;
   return PXD_OK;
 }
 
@@ -875,7 +940,14 @@ int pxd_sur_forward(pxd_sur* s, void* stream, int32_t B, const uint8_t* maps, fl
   if (int rc = check_batch(s, B)) return rc;
   SURCHK(s, hipSetDevice(s->cfg.device));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (int rc = forward(s, st, B, maps)) return rc;
+  if (s->plan.ok) {
+    int rc = pack_fused(s, st);
+    if (!rc) rc = head_v(s, st);
+    if (!rc) rc = forward_fused(s, st, B, maps);
+    if (rc) return rc;
+  } else if (int rc = forward(s, st, B, maps)) {
+    return rc;
+  }
   SURCHK(s, hipMemcpyAsync(out, s->out.p, 4 * (size_t)B * s->F * s->n_out, hipMemcpyDeviceToDevice, st));
   return PXD_OK;
 }
@@ -922,19 +994,40 @@ int pxd_sur_rank(pxd_sur* s, const pxd_ctx* ctx, void* stream, const uint8_t* ba
   SURCHK(s, hipSetDevice(s->cfg.device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int n_cells = s->cfg.n_layers * s->cfg.ny * s->cfg.nx;
+  if (s->plan.ok) {
+    int rc = pack_fused(s, st);
+    if (!rc) rc = head_v(s, st);
+    if (rc) return rc;
+  }
   for (int c0 = 0; c0 < n_cand; c0 += s->cfg.max_batch) {
     const int n = std::min(s->cfg.max_batch, n_cand - c0);
     hipLaunchKernelGGL(k_candidate_maps, dim3(n), dim3(256), 0, st, base_map, offsets, cells, c0, n, n_cells,
                        s->maps.as<uint8_t>());
     SURCHK(s, hipGetLastError());
-    if (int rc = forward(s, st, n, s->maps.as<uint8_t>())) return rc;
+    const int rc = s->plan.ok ? forward_fused(s, st, n, s->maps.as<uint8_t>()) : forward(s, st, n, s->maps.as<uint8_t>());
+    if (rc) return rc;
     const int* ei = s->ent.as<int>();
     hipLaunchKernelGGL(k_pred_fom, dim3((n + 3) / 4), dim3(256), 0, st, s->out.as<float>(), n, s->F,
                        s->cfg.n_entries, ei, ei + 4, t, fom_pred + c0);
     SURCHK(s, hipGetLastError());
   }
   if (k > 0) {
-    hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, fom_pred, n_cand, k, top);
+    // slices of 4,096 candidates (at most 256 of them), then one block over their top k each
+    const int G = std::min(256, (n_cand + 4095) / 4096);
+    if (G > 1 && k <= 256) {
+      const int per = (n_cand + G - 1) / G;
+      SURCHK(s, s->tk_v.ensure(sizeof(double) * (size_t)G * k));
+      SURCHK(s, s->tk_i.ensure(sizeof(int) * (size_t)G * k));
+      hipLaunchKernelGGL(k_topk, dim3(G), dim3(1024), 0, st, fom_pred, nullptr, n_cand, k, per, s->tk_v.as<double>(),
+                         s->tk_i.as<int>());
+      SURCHK(s, hipGetLastError());
+      hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, s->tk_v.as<double>(), s->tk_i.as<int>(), G * k, k,
+                         G * k, nullptr, top);
+    } else {
+      hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, fom_pred, nullptr, n_cand, k, n_cand, nullptr, top);
+    }
+    SURCHK(s, hipGetLastError());
+    hipLaunchKernelGGL(k_topk_ids, dim3((k + 255) / 256), dim3(256), 0, st, k, top);
     SURCHK(s, hipGetLastError());
   }
   return PXD_OK;

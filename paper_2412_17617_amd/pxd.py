@@ -444,6 +444,7 @@ class Graph:
 
 
 SUR_FP32, SUR_BF16 = 0, 1
+SUR_INFER_AUTO, SUR_INFER_GENERIC, SUR_INFER_FUSED = 0, 1, 2
 
 
 class SurConfig(C.Structure):
@@ -451,6 +452,7 @@ class SurConfig(C.Structure):
         ("device", C.c_int32), ("n_layers", C.c_int32), ("ny", C.c_int32), ("nx", C.c_int32),
         ("channels", C.c_int32 * 4), ("hidden", C.c_int32), ("emb", C.c_int32), ("n_entries", C.c_int32),
         ("entry_i", C.c_int32 * 4), ("entry_j", C.c_int32 * 4), ("precision", C.c_int32), ("max_batch", C.c_int32),
+        ("inference", C.c_int32),
     ]
 
 
@@ -472,6 +474,7 @@ _SIGS.update({
     "pxd_sur_train_step": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, C.POINTER(AdamW), _VP]),
     "pxd_sur_rank": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, _VP, _VP, C.c_int32, _VP, _VP]),
     "pxd_sur_encode": (C.c_int, [_VP, _VP, C.c_int32, _VP, C.c_int32, _VP]),
+    "pxd_sur_inference_path": (C.c_int, [_VP, _VP]),
 })
 
 
@@ -481,7 +484,8 @@ class Surrogate:
     None (HIP's default stream)."""
 
     def __init__(self, n_layers, ny, nx, freqs, f_lo, f_hi, entries=((0, 0), (1, 0), (2, 0)),
-                 channels=(32, 32, 64, 64), hidden=256, emb=16, precision=SUR_BF16, max_batch=64, device=0):
+                 channels=(32, 32, 64, 64), hidden=256, emb=16, precision=SUR_BF16, max_batch=64, device=0,
+                 inference=SUR_INFER_AUTO):
         c = SurConfig()
         c.device, c.n_layers, c.ny, c.nx = device, n_layers, ny, nx
         for i in range(4):
@@ -489,7 +493,7 @@ class Surrogate:
         c.hidden, c.emb, c.n_entries = hidden, emb, len(entries)
         for k, (i, j) in enumerate(entries):
             c.entry_i[k], c.entry_j[k] = i, j
-        c.precision, c.max_batch = precision, max_batch
+        c.precision, c.max_batch, c.inference = precision, max_batch, inference
         freqs = np.ascontiguousarray(freqs, np.float64)
         h_ = _VP()
         _check(lib().pxd_sur_create(C.byref(c), len(freqs), _ptr(freqs), f_lo, f_hi, C.byref(h_)))
@@ -498,6 +502,9 @@ class Surrogate:
         n = C.c_int64()
         self._c(lib().pxd_sur_num_params(self._h, C.byref(n)))
         self.n_params = n.value
+        path = C.c_int32()
+        self._c(lib().pxd_sur_inference_path(self._h, C.byref(path)))
+        self.inference = path.value
 
     def _c(self, rc):
         if rc != OK:

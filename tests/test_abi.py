@@ -85,3 +85,18 @@ def test_fill_rejects_bad_sizes():
     pb = pxd.Problem.from_spec(get_spec("tiny3"))
     rc = pxd.lib().pxd_problem_fill(pb._h, 0, None, None, 1)
     assert rc == pxd.EINVAL
+
+
+def test_fused_surrogate_inference_is_refused_where_it_does_not_apply():
+    # checked before any device call: 4 x 4 maps (the pooled planes are not
+    # whole 4 x 4 blocks), a channel count other than 16/32/64, FP32 products
+    freqs = np.linspace(1e9, 2e9, 3)
+    for kw in (dict(ny=4, nx=4), dict(ny=8, nx=8, channels=(32, 48, 64, 64)),
+               dict(ny=8, nx=8, precision=pxd.SUR_FP32)):
+        ny, nx = kw.pop("ny"), kw.pop("nx")
+        with pytest.raises(pxd.PxdError) as e:
+            pxd.Surrogate(1, ny, nx, freqs, freqs[0], freqs[-1], inference=pxd.SUR_INFER_FUSED, **kw)
+        assert e.value.code == pxd.EINVAL
+    with pytest.raises(pxd.PxdError) as e:
+        pxd.Surrogate(1, 8, 8, freqs, freqs[0], freqs[-1], inference=3)
+    assert e.value.code == pxd.EINVAL

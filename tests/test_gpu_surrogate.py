@@ -401,3 +401,138 @@ def test_device_encoding_matches_host_encoding():
     got = tgt.cpu().numpy()
     s.close()
     assert np.allclose(got, ref, rtol=1e-6, atol=1e-6), np.abs(got - ref).max()
+
+
+# ---------------------------------------------------------------- fused inference
+
+# (network, frequencies, max_batch): the 8 x 8 and working-size nets, a 32 x 32
+# map (one workgroup per CU: 124 KB of LDS), and mixed channel counts with one
+# and eight input planes.
+FUSED = [
+    (osur.SurrogateConfig(n_layers=3, ny=8, nx=8, channels=(32, 32, 64, 64), hidden=64, emb=16, n_out=9), 7, 8),
+    (osur.SurrogateConfig(n_layers=3, ny=24, nx=24, channels=(32, 32, 64, 64), hidden=256, emb=16, n_out=9), 101, 64),
+    (osur.SurrogateConfig(n_layers=3, ny=32, nx=32, channels=(32, 32, 64, 64), hidden=256, emb=16, n_out=9), 21, 16),
+    (osur.SurrogateConfig(n_layers=1, ny=16, nx=8, channels=(16, 32, 16, 64), hidden=32, emb=8, n_out=6), 5, 16),
+    (osur.SurrogateConfig(n_layers=8, ny=8, nx=16, channels=(64, 16, 32, 32), hidden=128, emb=16, n_out=12), 9, 16),
+]
+ALL_ENTRIES = ((0, 0), (1, 0), (2, 0), (2, 1))
+
+
+def fused_pair(cfg, freqs, max_batch):
+    kw = dict(entries=ALL_ENTRIES[:cfg.n_out // 3], channels=cfg.channels, hidden=cfg.hidden, emb=cfg.emb,
+              precision=pxd.SUR_BF16, max_batch=max_batch)
+    f = pxd.Surrogate(cfg.n_layers, cfg.ny, cfg.nx, freqs, freqs[0], freqs[-1], **kw)
+    g = pxd.Surrogate(cfg.n_layers, cfg.ny, cfg.nx, freqs, freqs[0], freqs[-1],
+                      inference=pxd.SUR_INFER_GENERIC, **kw)
+    return f, g
+
+
+@pytest.mark.parametrize("i", range(len(FUSED)))
+def test_fused_inference_matches_generic_and_oracle(i):
+    """The fused kernels against the generic BF16 products (same operand
+    rounding; FP32 sums in another order, and an activation on either side of
+    a BF16 rounding boundary can round the other way: 5e-3 norm-wise) and
+    against the FP64 oracle (the BF16 bar above, 2e-2)."""
+    cfg, F, mb = FUSED[i]
+    freqs = np.linspace(2e9, 7e9, F)
+    fu, ge = fused_pair(cfg, freqs, mb)
+    assert fu.inference == pxd.SUR_INFER_FUSED and ge.inference == pxd.SUR_INFER_GENERIC
+    p32 = init_params(cfg, 20 + i).astype(np.float32)
+    fu.set_params(p32)
+    ge.set_params(p32)
+    B = min(mb, 5)
+    maps = random_maps(B, cfg.n_layers * cfg.ny * cfg.nx, 30 + i)
+    tm = torch.from_numpy(maps).to(DEV)
+    outs = []
+    for s in (fu, ge):
+        o = torch.full((B, F, cfg.n_out), float("nan"), dtype=torch.float32, device=DEV)
+        s.forward(tm, o)
+        outs.append(o.cpu().numpy())
+    want, _ = osur.forward(p32.astype(np.float64), maps, u_of(freqs), cfg)
+    print(f"fused vs generic {rel(outs[0], outs[1]):.2e}, fused vs oracle {rel(outs[0], want):.2e}, "
+          f"generic vs oracle {rel(outs[1], want):.2e}")
+    assert np.isfinite(outs[0]).all()
+    assert rel(outs[0], outs[1]) <= 5e-3
+    assert rel(outs[0], want) <= 2e-2
+    fu.close()
+    ge.close()
+
+
+def test_fused_inference_at_max_batch():
+    """2,048 working-size maps in one call (2,048 trunk workgroups, 512 head
+    blocks) against the generic products, per map."""
+    cfg, F, _ = FUSED[1]
+    freqs = np.linspace(1e9, 8e9, F)
+    fu, ge = fused_pair(cfg, freqs, 2048)
+    p32 = init_params(cfg, 40).astype(np.float32)
+    fu.set_params(p32)
+    ge.set_params(p32)
+    maps = random_maps(2048, 3 * 24 * 24, 41, p=0.3)
+    tm = torch.from_numpy(maps).to(DEV)
+    outs = []
+    for s in (fu, ge):
+        o = torch.full((2048, F, 9), float("nan"), dtype=torch.float32, device=DEV)
+        s.forward(tm, o)
+        outs.append(o.cpu().numpy())
+    per_map = np.array([rel(outs[0][b], outs[1][b]) for b in range(2048)])
+    print(f"fused vs generic per map: max {per_map.max():.2e}, median {np.median(per_map):.2e}")
+    assert np.isfinite(outs[0]).all() and per_map.max() <= 1e-2
+    fu.close()
+    ge.close()
+
+
+SPEC8 = spec_variant("small6x3", n_layers=2, nx=8, ny=8, a=1e-3, n_freq=9, f_lo=3e9, f_hi=8e9, seed=33,
+                     ports=(PortSpec("right", 0), PortSpec("top", 1), PortSpec("left", 0)))
+
+
+def test_fused_ranking_is_the_fom_of_its_predictions():
+    """pxd_sur_rank on the fused path (2 x 8 x 8 maps, every single flip and
+    every pair of the first 24 cells, batches of 256): fom_pred against the
+    FoM the oracle computes from the fused forward outputs of sampled
+    candidates, top-k against a sort, and close to the generic path's fom_pred."""
+    from oracle import fom as ofom
+
+    freqs = SPEC8.freqs
+    pb = pxd.Problem.from_spec(SPEC8)
+    ev = pxd.Evaluator(precision=pxd.PREC_FP64)
+    ev.load_parent(pb.fill(freqs, n_threads=16), freqs)
+    ev.load_problem(pb, SPEC8.z0)
+    ev.set_fom_paper()
+    cfg = osur.SurrogateConfig(n_layers=2, ny=8, nx=8, channels=(32, 32, 64, 64), hidden=128, emb=16, n_out=12)
+    fu, ge = fused_pair(cfg, freqs, 256)
+    assert fu.inference == pxd.SUR_INFER_FUSED
+    p32 = init_params(cfg, 50).astype(np.float32)
+    fu.set_params(p32)
+    ge.set_params(p32)
+    n = 2 * 64
+    iu, ju = np.triu_indices(24, 1)
+    off = np.concatenate([np.arange(n + 1), n + 2 * np.arange(1, len(iu) + 1)]).astype(np.int32)
+    cells = np.concatenate([np.arange(n), np.stack([iu, ju], 1).ravel()]).astype(np.int32)
+    C = len(off) - 1
+    base = SPEC8.base_map()
+    fps = []
+    for s in (fu, ge):
+        fp = torch.zeros(C, dtype=torch.float64, device=DEV)
+        top = torch.zeros(16, dtype=torch.int32, device=DEV)
+        s.rank(ev, torch.from_numpy(base).to(DEV), torch.from_numpy(off).to(DEV), torch.from_numpy(cells).to(DEV),
+               16, fp, top)
+        torch.cuda.synchronize()
+        fps.append((fp.cpu().numpy(), top.cpu().numpy()))
+    fp, top = fps[0]
+    assert np.array_equal(top, np.argsort(fp, kind="stable")[:16])
+    assert np.max(np.abs(fp - fps[1][0]) / fps[1][0]) <= 5e-2
+    pick = np.array([0, 1, 127, 128, C - 1, int(top[0])])
+    maps = np.repeat(base[None], len(pick), 0)
+    for r, c in enumerate(pick):
+        maps[r, cells[off[c]:off[c + 1]]] ^= 1
+    out = torch.zeros((len(pick), len(freqs), 12), dtype=torch.float32, device=DEV)
+    fu.forward(torch.from_numpy(maps).to(DEV), out)
+    o = out.cpu().numpy().astype(np.float64)
+    for r in range(len(pick)):
+        S = np.zeros((len(freqs), 3, 3), np.complex128)
+        for e, (i, j) in enumerate(ALL_ENTRIES):
+            S[:, i, j] = np.exp(o[r, :, 3 * e])
+        assert abs(ofom.fom(S, freqs) - fp[pick[r]]) <= 1e-9 * fp[pick[r]]
+    fu.close()
+    ge.close()
+    ev.close()
