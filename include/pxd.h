@@ -428,7 +428,7 @@ void pxd_graph_destroy(pxd_graph* g);
  * the generic products).  FUSED: the four convolutions of one map run in one
  * workgroup with BF16 activations held in LDS, and the head's output layer
  * forms its hidden activations in registers; BF16 only, ny and nx multiples
- * of 8, n_layers <= 8, channels each 16, 32 or 64, hidden a power of two
+ * of 8, n_layers <= 8, channels each 32 or 64, hidden a power of two
  * >= 32.  Same operand rounding as the generic BF16 products, FP32 sums in
  * another order.  AUTO takes FUSED where it applies, else GENERIC. */
 #define PXD_SUR_INFER_AUTO 0

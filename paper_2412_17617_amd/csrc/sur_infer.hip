@@ -24,8 +24,8 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 4;        // waves per trunk workgroup
-constexpr int kMB = 6, kNB = 2;  // largest wave task: row tiles x column tiles
+constexpr int kWaves = 4;  // waves per trunk workgroup
+constexpr int kMB = 5;     // most row tiles per wave task (column tiles per task: 2)
 constexpr int kHeadFT = 8;       // frequency tiles (16 each) per head pass
 
 // FP32 -> BF16 bits, round to nearest even, inf and NaN kept
@@ -38,11 +38,15 @@ __device__ __forceinline__ unsigned short bf16_bits(float f) {
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// floor(i / d) with m = ceil(2^20 / d), exact for 0 <= i < 4096 and
+// 2 <= d <= 64 (the error i (m - 2^20 / d) / 2^20 stays below 1 / d), and for
+// i < 2048 when d = 1 (the product stays below 2^31)
+__device__ __forceinline__ int div_small(int i, int m) { return (i * m) >> 20; }
+
 // Zero the one-pixel border of an H x W buffer (pixel stride cs, row stride rs).
 __device__ void zero_border(unsigned short* lds, int off, int H, int W, int cs, int rs, int tid) {
   const int cpp = cs >> 3, npix = 2 * (W + 2) + 2 * H;
-  for (int i = tid; i < npix * cpp; i += 64 * kWaves) {
-    const int pix = i / cpp, c = i - pix * cpp;
+  for (int pix = tid; pix < npix; pix += 64 * kWaves) {
     int y, x;
     if (pix < W + 2) {
       y = 0, x = pix;
@@ -52,91 +56,104 @@ __device__ void zero_border(unsigned short* lds, int off, int H, int W, int cs, 
       const int r = pix - 2 * (W + 2);
       y = 1 + (r >> 1), x = (r & 1) ? W + 1 : 0;
     }
-    *reinterpret_cast<uint4*>(lds + off + y * rs + x * cs + 8 * c) = make_uint4(0, 0, 0, 0);
+    for (int c = 0; c < cpp; ++c) *reinterpret_cast<uint4*>(lds + off + y * rs + x * cs + 8 * c) = make_uint4(0, 0, 0, 0);
   }
 }
 
 struct TrunkArgs {
   InferLayer l[4];
   const uint8_t* maps;
-  int n_layers, n_cells;
+  int n_layers, n_cells, m_w, zero_off;
   const uint4* frag;
   const float* bias[4];
   unsigned short* a4;  // BF16 [B][H/4][W/4][channels[3]]
 };
 
-// One convolution layer of one map, all waves of the workgroup; KS (the
-// layer's k steps) is a template constant so that the k loop is unrolled and
-// the weight fragments of up to nine steps (x nb column tiles) sit in
+// One convolution layer of one map, all waves of the workgroup.  The task
+// shape is compile-time: KS k steps (9 x 8, 32 or 64 padded input channels),
+// MB row tiles, two column tiles, so the k loop is unrolled with no branch
+// around a load or an MFMA.  The weight fragments of up to nine steps sit in
 // registers: loaded once per column group when the whole layer fits, else
-// per half of the k range.
-template <int KS>
+// per half of the k range.  A partial last chunk of row tiles repeats its
+// last tile (the repeat is not stored); padding taps read a zero chunk.
+template <int KS, int MB>
 __device__ __forceinline__ void conv_layer(const InferLayer& L, const uint4* __restrict__ wf,
-                                           const float* __restrict__ bias, unsigned short* lds,
+                                           const float* __restrict__ bias, unsigned short* lds, int zero_off,
                                            unsigned short* __restrict__ a4_map, bool last, int wave, int lane) {
-  constexpr int KH = KS > 9 ? 9 : KS;  // k steps whose weights are held at once
-  static_assert(KS % KH == 0, "k steps in whole halves");
+  constexpr int NB = 2;
+  constexpr int KH = KS > 9 ? 9 : KS;                          // k steps whose weights are held at once
+  constexpr int CSH = KS == 3 ? 3 : (KS == 9 ? 5 : 6);         // log2 of the padded input channels
+  constexpr bool PAD = 32 * KS > 9 * (1 << CSH);               // steps reach past the nine taps
+  static_assert(KS % KH == 0 && (KS == 3 || KS == 9 || KS == 18), "k steps");
   const int wt = L.W >> 2, T = (L.H >> 2) * wt;
-  const int nch = (T + L.mb - 1) / L.mb, ngr = (L.nt + L.nb - 1) / L.nb;
+  const int nch = (T + MB - 1) / MB, ngr = L.nt / NB;
   const int r = lane & 15, q = lane >> 4;
-  const int cmask = (1 << L.cin_sh) - 1;
-  bf16x8 bw[KH][kNB];
+  bf16x8 bw[KH][NB];
   int loaded = -1;
   for (int task = wave; task < nch * ngr; task += kWaves) {
-    const int t0 = (task % nch) * L.mb, n0 = (task / nch) * L.nb;
-    // A row r of tile t is pixel (4 by + r / 4, 4 bx + r % 4)
-    int abase[kMB];
+    const int gi = div_small(task, L.m_nch), t0 = (task - gi * nch) * MB, n0 = gi * NB;
+    if (KS != KH || n0 != loaded) {
 #pragma unroll
-    for (int m = 0; m < kMB; ++m) {
-      const int t = min(t0 + m, T - 1);
-      const int by = t / wt, bx = t - by * wt;
-      abase[m] = L.in_off + (4 * by + (r >> 2) + 1) * L.in_rs + (4 * bx + (r & 3) + 1) * L.in_cs;
+      for (int h = 0; h < KH; ++h)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) bw[h][n] = as_bf16x8(wf[((size_t)(n0 + n) * KS + h) * 64 + lane]);
+      loaded = n0;
     }
-    f4 acc[kMB][kNB];
+    // A row r of tile t is pixel (4 by + r / 4, 4 bx + r % 4); lanes q take channels 8 q .. + 7
+    int abase[MB];
 #pragma unroll
-    for (int m = 0; m < kMB; ++m)
+    for (int m = 0; m < MB; ++m) {
+      const int t = min(t0 + m, T - 1);
+      const int by = div_small(t, L.m_wt), bx = t - by * wt;
+      abase[m] = L.in_off + (4 * by + (r >> 2) + 1) * L.in_rs + (4 * bx + (r & 3) + 1) * L.in_cs +
+                 (CSH >= 5 ? 8 * q : 0);
+    }
+    f4 acc[MB][NB];
 #pragma unroll
-      for (int n = 0; n < kNB; ++n) acc[m][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int n = 0; n < NB; ++n) acc[m][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int c = 0; c < KS / KH; ++c) {
-      if (KS != KH || n0 != loaded) {
+      if (c > 0) {  // second half of an 18-step layer
 #pragma unroll
         for (int h = 0; h < KH; ++h)
 #pragma unroll
-          for (int n = 0; n < kNB; ++n)
-            if (n < L.nb && n0 + n < L.nt)
-              bw[h][n] = as_bf16x8(wf[((size_t)(n0 + n) * KS + c * KH + h) * 64 + lane]);
-        loaded = n0;
+          for (int n = 0; n < NB; ++n) bw[h][n] = as_bf16x8(wf[((size_t)(n0 + n) * KS + c * KH + h) * 64 + lane]);
+        loaded = -1;
       }
 #pragma unroll
       for (int h = 0; h < KH; ++h) {
-        // lane k values 32 s + 8 q .. + 7: one tap, eight consecutive channels
-        const int kb = 32 * (c * KH + h) + 8 * q, tap = kb >> L.cin_sh;
-        const bool ok = tap < 9;  // k beyond 9 x cin is padding
-        const int tp = ok ? tap : 4, ty = tp / 3;
-        const int toff = (ty - 1) * L.in_rs + (tp - 3 * ty - 1) * L.in_cs + (kb & cmask);
+        const int s = c * KH + h;
+        // k = 32 s + 8 q .. + 7 is one tap and eight consecutive (padded) channels
+        int toff;
+        bool ok = true;
+        if constexpr (CSH >= 5) {  // the tap and channel base are the same for every lane
+          const int tap = (32 * s) >> CSH, ty = tap / 3, tx = tap - 3 * ty;
+          toff = (ty - 1) * L.in_rs + (tx - 1) * L.in_cs + ((32 * s) & ((1 << CSH) - 1));
+        } else {  // eight channels per tap: lane group q takes tap 4 s + q
+          const int tap = 4 * s + q;
+          const int ty = (tap * 11) >> 5, tx = tap - 3 * ty;  // tap / 3 for tap < 12
+          if (PAD) ok = tap < 9;
+          toff = (ty - 1) * L.in_rs + (tx - 1) * L.in_cs;
+        }
 #pragma unroll
-        for (int m = 0; m < kMB; ++m) {
-          if (m < L.mb && t0 + m < T) {
-            uint4 v = *reinterpret_cast<const uint4*>(lds + abase[m] + toff);
-            if (!ok) v = make_uint4(0, 0, 0, 0);
-            const bf16x8 a = as_bf16x8(v);
+        for (int m = 0; m < MB; ++m) {
+          const int addr = ok ? abase[m] + toff : zero_off;
+          const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4*>(lds + addr));
 #pragma unroll
-            for (int n = 0; n < kNB; ++n)
-              if (n < L.nb && n0 + n < L.nt)
-                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[h][n], acc[m][n], 0, 0, 0);
-          }
+          for (int n = 0; n < NB; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[h][n], acc[m][n], 0, 0, 0);
         }
       }
     }
     // accumulator element i of lane (q, r): pixel (4 by + q, 4 bx + i), channel 16 tile + r
 #pragma unroll
-    for (int m = 0; m < kMB; ++m) {
-      if (!(m < L.mb && t0 + m < T)) continue;
-      const int t = t0 + m, by = t / wt, bx = t - by * wt;
+    for (int m = 0; m < MB; ++m) {
+      if (t0 + m >= T) continue;  // repeated tile
+      const int t = t0 + m, by = div_small(t, L.m_wt), bx = t - by * wt;
 #pragma unroll
-      for (int n = 0; n < kNB; ++n) {
-        if (!(n < L.nb && n0 + n < L.nt)) continue;
+      for (int n = 0; n < NB; ++n) {
         const int col = 16 * (n0 + n) + r;
         const float bc = bias[col];
         const f4 z = acc[m][n];
@@ -174,16 +191,30 @@ __device__ __forceinline__ void conv_layer(const InferLayer& L, const uint4* __r
   }
 }
 
+template <int KS>
+__device__ __forceinline__ void conv_mb(const InferLayer& L, const uint4* wf, const float* bias, unsigned short* lds,
+                                        int zero_off, unsigned short* a4_map, bool last, int wave, int lane) {
+  switch (L.mb) {
+    case 1: conv_layer<KS, 1>(L, wf, bias, lds, zero_off, a4_map, last, wave, lane); break;
+    case 2: conv_layer<KS, 2>(L, wf, bias, lds, zero_off, a4_map, last, wave, lane); break;
+    case 3: conv_layer<KS, 3>(L, wf, bias, lds, zero_off, a4_map, last, wave, lane); break;
+    case 4: conv_layer<KS, 4>(L, wf, bias, lds, zero_off, a4_map, last, wave, lane); break;
+    default: conv_layer<KS, 5>(L, wf, bias, lds, zero_off, a4_map, last, wave, lane); break;
+  }
+}
+
 __global__ __launch_bounds__(64 * kWaves) void k_trunk(TrunkArgs p) {
   extern __shared__ __align__(16) unsigned short lds[];
   const int b = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int zero_off = p.zero_off;  // a 16-byte zero chunk after the two regions
+  if (tid == 0) *reinterpret_cast<uint4*>(lds + zero_off) = make_uint4(0, 0, 0, 0);
   // input planes -> layer 0's buffer (eight channels, the first n_layers used)
   {
     const InferLayer& L = p.l[0];
     const uint8_t* mp = p.maps + (size_t)b * p.n_cells;
     const int hw = L.H * L.W;
     for (int i = tid; i < hw; i += 64 * kWaves) {
-      const int y = i / L.W, x = i - y * L.W;
+      const int y = div_small(i, p.m_w), x = i - y * L.W;
       unsigned short v[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) v[c] = (c < p.n_layers && mp[(size_t)c * hw + i]) ? 0x3F80 : 0;  // BF16 1.0
@@ -206,11 +237,10 @@ __global__ __launch_bounds__(64 * kWaves) void k_trunk(TrunkArgs p) {
       zero_border(lds, L.out_off, ho, wo, L.out_cs, L.out_rs, tid);
     }
     const uint4* wf = p.frag + (size_t)L.frag * 64;
-    switch (L.ks) {  // 9 x (8, 16, 32, 64) padded input channels in 32-deep steps
-      case 3: conv_layer<3>(L, wf, p.bias[li], lds, a4_map, li == 3, wave, lane); break;
-      case 5: conv_layer<5>(L, wf, p.bias[li], lds, a4_map, li == 3, wave, lane); break;
-      case 9: conv_layer<9>(L, wf, p.bias[li], lds, a4_map, li == 3, wave, lane); break;
-      default: conv_layer<18>(L, wf, p.bias[li], lds, a4_map, li == 3, wave, lane); break;
+    switch (L.ks) {  // 9 x (8, 32, 64) padded input channels in 32-deep steps
+      case 3: conv_mb<3>(L, wf, p.bias[li], lds, zero_off, a4_map, li == 3, wave, lane); break;
+      case 9: conv_mb<9>(L, wf, p.bias[li], lds, zero_off, a4_map, li == 3, wave, lane); break;
+      default: conv_mb<18>(L, wf, p.bias[li], lds, zero_off, a4_map, li == 3, wave, lane); break;
     }
     __syncthreads();
   }
@@ -261,15 +291,13 @@ __global__ __launch_bounds__(256) void k_head_u(int B, int feat, int ks, int nt,
   for (int s = 0; s < ks; ++s) {
     const bf16x8 a = as_bf16x8(arow[4 * s]);  // k = 32 s + 8 q .. + 7
 #pragma unroll
-    for (int n = 0; n < kUNT; ++n)
-      if (kUNT * g + n < nt)
-        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            a, as_bf16x8(wf[((size_t)(kUNT * g + n) * ks + s) * 64 + lane]), acc[n], 0, 0, 0);
+    for (int n = 0; n < kUNT; ++n)  // nt is even (hidden a power of two >= 32)
+      acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          a, as_bf16x8(wf[((size_t)(kUNT * g + n) * ks + s) * 64 + lane]), acc[n], 0, 0, 0);
   }
   const int hd = 16 * nt;
 #pragma unroll
   for (int n = 0; n < kUNT; ++n) {
-    if (kUNT * g + n >= nt) continue;
     const int col = 16 * (kUNT * g + n) + r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -299,8 +327,7 @@ __global__ __launch_bounds__(256) void k_head(int B, int F, int hd, int ks, int 
 #pragma unroll
       for (int e = 0; e < 8; ++e) uu[e] = U[(size_t)b * hd + k + e], cc[e] = bh[k + e];
 #pragma unroll
-      for (int t = 0; t < kHeadFT; ++t) {
-        if (f0 + 16 * t >= F) continue;  // wave-uniform
+      for (int t = 0; t < kHeadFT; ++t) {  // rows past F are zero and not stored
         const int f = f0 + 16 * t + r;
         const float* vr = V + (size_t)min(f, F - 1) * hd + k;
         float vv[8];
@@ -342,6 +369,8 @@ void buffer_layout(int H, int W, int C, int* cs, int* rs, int* elems) {
   *elems = (H + 2) * *rs;
 }
 
+int magic(int d) { return ((1 << 20) + d - 1) / d; }
+
 int log2_exact(int v) {
   int s = 0;
   while ((1 << s) < v) ++s;
@@ -367,7 +396,7 @@ InferPlan infer_plan(int n_layers, int ny, int nx, const int channels[4], int hi
   if (n_layers < 1 || n_layers > 8 || ny % 8 || nx % 8 || ny < 8 || nx < 8) return p;
   for (int i = 0; i < 4; ++i) {
     const int c = channels[i];
-    if (c != 16 && c != 32 && c != 64) return p;
+    if (c != 32 && c != 64) return p;
   }
   if (hidden < 32 || log2_exact(hidden) < 0 || n_out < 1 || n_out > 16) return p;
   p.L = n_layers, p.H = ny, p.W = nx;
@@ -382,7 +411,8 @@ InferPlan infer_plan(int n_layers, int ny, int nx, const int channels[4], int hi
   // region A (a1, then a3) at 0, region B (in0, then a2) after it
   const int regA = std::max(el[1], el[3]), regB = std::max(el[0], el[2]);
   const int off[4] = {regA, 0, regA, 0};
-  p.lds_bytes = 2 * (regA + regB);
+  p.zero_off = regA + regB;
+  p.lds_bytes = 2 * (regA + regB) + 16;
   if (p.lds_bytes > 160 * 1024) return p;
   for (int i = 0; i < 4; ++i) {
     InferLayer& L = p.l[i];
@@ -396,8 +426,11 @@ InferPlan infer_plan(int n_layers, int ny, int nx, const int channels[4], int hi
     L.in_off = off[i], L.in_cs = cs[i], L.in_rs = rs[i];
     if (i < 3) L.out_off = off[i + 1], L.out_cs = cs[i + 1], L.out_rs = rs[i + 1];
     L.pool = (i == 1 || i == 3);
-    L.nb = std::min(L.nt, kNB);
-    L.mb = pick_mb((L.H / 4) * (L.W / 4), (L.nt + L.nb - 1) / L.nb);
+    L.nb = 2;
+    const int T = (L.H / 4) * (L.W / 4);
+    L.mb = pick_mb(T, L.nt / 2);
+    L.m_wt = magic(L.W / 4);
+    L.m_nch = magic((T + L.mb - 1) / L.mb);
     L.frag = frag;
     frag += L.nt * L.ks;
   }
@@ -440,7 +473,7 @@ hipError_t infer_trunk(hipStream_t st, const InferPlan& p, int B, const uint8_t*
   if (B <= 0) return hipSuccess;
   TrunkArgs a;
   for (int i = 0; i < 4; ++i) a.l[i] = p.l[i], a.bias[i] = bias[i];
-  a.maps = maps, a.n_layers = p.L, a.n_cells = n_cells;
+  a.maps = maps, a.n_layers = p.L, a.n_cells = n_cells, a.m_w = magic(p.W), a.zero_off = p.zero_off;
   a.frag = static_cast<const uint4*>(frag);
   a.a4 = static_cast<unsigned short*>(a4);
   hipLaunchKernelGGL(k_trunk, dim3(B), dim3(64 * kWaves), p.lds_bytes, st, a);

@@ -25,6 +25,7 @@ struct InferLayer {
   int out_off, out_cs, out_rs;   // output buffer in LDS (not used by the last layer)
   int pool;                      // 2 x 2 average pool after the ReLU
   int mb, nb;                    // row tiles and column tiles per wave task
+  int m_wt, m_nch;               // ceil(2^20 / d) for d = W / 4 and the row chunks (division by multiply)
   int frag;                      // first weight fragment (64 lanes x 16 bytes each)
 };
 
@@ -33,6 +34,7 @@ struct InferPlan {
   InferLayer l[4];
   int L = 0, H = 0, W = 0;       // map shape
   int lds_bytes = 0;
+  int zero_off = 0;              // LDS element offset of a 16-byte zero chunk
   int feat = 0, ks_u = 0;         // head input features (NHWC of the last pooled plane), k steps
   int u_frag = 0;                // first fragment of the head's first-layer weights
   int hidden = 0, ks_head = 0, n_out = 0;
