@@ -28,12 +28,14 @@ constexpr int kWaves = 4;  // waves per trunk workgroup
 constexpr int kMB = 5;     // most row tiles per wave task (column tiles per task: 2)
 constexpr int kHeadFT = 8;       // frequency tiles (16 each) per head pass
 
-// FP32 -> BF16 bits, round to nearest even, inf and NaN kept
-__device__ __forceinline__ unsigned short bf16_bits(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// FP32 -> BF16 bits, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ unsigned short bf16_bits(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
+
+// two FP32 -> packed BF16 (low half first)
+__device__ __forceinline__ unsigned bf16_pair(float lo, float hi) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(unsigned, v);
 }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
@@ -274,26 +276,45 @@ __global__ void k_pack(const float* __restrict__ w, int taps, int cin, int sh, i
 // First head layer without its bias: U = a4 Wf, rows the maps, k the
 // features in NHWC order, columns the hidden units.  A wave takes 16 maps x
 // kUNT column tiles; the four waves of a block take four consecutive map
-// tiles of the same columns, so their weight fragments are shared in L1.
-constexpr int kUNT = 2;
+// tiles of the same columns, so their weight fragments are shared in L1.  The
+// k loop runs in stages of kUC steps with the next stage's loads in flight.
+constexpr int kUNT = 2, kUC = 4;
 __global__ __launch_bounds__(256) void k_head_u(int B, int feat, int ks, int nt, const unsigned short* __restrict__ a4,
                                                 const uint4* __restrict__ wf, float* __restrict__ U) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ngr = (nt + kUNT - 1) / kUNT;
+  const int ngr = nt / kUNT;  // nt is even (hidden a power of two >= 32)
   const int g = blockIdx.x % ngr, mt = (blockIdx.x / ngr) * 4 + wave;
   if (16 * mt >= B) return;  // whole waves leave together
   const int r = lane & 15, q = lane >> 4;
+  // lane (q, r): map 16 mt + r, k = 32 s + 8 q .. + 7
   const uint4* arow = reinterpret_cast<const uint4*>(a4 + (size_t)min(16 * mt + r, B - 1) * feat) + q;
+  const uint4* wcol = wf + (size_t)kUNT * g * ks * 64 + lane;  // fragment (kUNT g + n, s) at (n ks + s) 64
   f4 acc[kUNT];
 #pragma unroll
   for (int n = 0; n < kUNT; ++n) acc[n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-  for (int s = 0; s < ks; ++s) {
-    const bf16x8 a = as_bf16x8(arow[4 * s]);  // k = 32 s + 8 q .. + 7
+  uint4 A0[kUC], B0[kUC][kUNT], A1[kUC], B1[kUC][kUNT];
+  auto load = [&](uint4(&A)[kUC], uint4(&Bw)[kUC][kUNT], int s0) {
 #pragma unroll
-    for (int n = 0; n < kUNT; ++n)  // nt is even (hidden a power of two >= 32)
-      acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-          a, as_bf16x8(wf[((size_t)(kUNT * g + n) * ks + s) * 64 + lane]), acc[n], 0, 0, 0);
+    for (int h = 0; h < kUC; ++h) {
+      A[h] = arow[4 * (s0 + h)];
+#pragma unroll
+      for (int n = 0; n < kUNT; ++n) Bw[h][n] = wcol[((size_t)n * ks + s0 + h) * 64];
+    }
+  };
+  auto mul = [&](const uint4(&A)[kUC], const uint4(&Bw)[kUC][kUNT]) {
+#pragma unroll
+    for (int h = 0; h < kUC; ++h)
+#pragma unroll
+      for (int n = 0; n < kUNT; ++n)
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[h]), as_bf16x8(Bw[h][n]), acc[n], 0, 0, 0);
+  };
+  const int nc = ks / kUC;  // ks is a multiple of 4: (H / 4) (W / 4) is
+  load(A0, B0, 0);
+  for (int c = 0; c < nc; c += 2) {
+    if (c + 1 < nc) load(A1, B1, (c + 1) * kUC);
+    mul(A0, B0);
+    if (c + 2 < nc) load(A0, B0, (c + 2) * kUC);
+    if (c + 1 < nc) mul(A1, B1);
   }
   const int hd = 16 * nt;
 #pragma unroll
@@ -308,7 +329,8 @@ __global__ __launch_bounds__(256) void k_head_u(int B, int feat, int ks, int nt,
 }
 
 // Head output layer, one wave per map: rows are frequencies (16 per MFMA
-// tile), k the hidden units, columns the outputs (one 16-wide tile).
+// tile), k the hidden units, columns the outputs (one 16-wide tile); the
+// hidden activations relu((U[b] + V[f]) + bh) are formed in registers.
 __global__ __launch_bounds__(256) void k_head(int B, int F, int hd, int ks, int n_out, const float* __restrict__ U,
                                               const float* __restrict__ V, const float* __restrict__ bh,
                                               const uint4* __restrict__ wf, const float* __restrict__ bo,
@@ -323,24 +345,23 @@ __global__ __launch_bounds__(256) void k_head(int B, int F, int hd, int ks, int 
     for (int s = 0; s < ks; ++s) {
       const int k = 32 * s + 8 * q;
       const bf16x8 w = as_bf16x8(wf[(size_t)s * 64 + lane]);
-      float uu[8], cc[8];
+      const float4 u0 = *reinterpret_cast<const float4*>(U + (size_t)b * hd + k);
+      const float4 u1 = *reinterpret_cast<const float4*>(U + (size_t)b * hd + k + 4);
+      float c[8];  // the parameter vector need not be 16-byte aligned
 #pragma unroll
-      for (int e = 0; e < 8; ++e) uu[e] = U[(size_t)b * hd + k + e], cc[e] = bh[k + e];
+      for (int e = 0; e < 8; ++e) c[e] = bh[k + e];
 #pragma unroll
       for (int t = 0; t < kHeadFT; ++t) {  // rows past F are zero and not stored
         const int f = f0 + 16 * t + r;
         const float* vr = V + (size_t)min(f, F - 1) * hd + k;
-        float vv[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) vv[e] = vr[e];
-        unsigned short h[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) h[e] = f < F ? bf16_bits(fmaxf((uu[e] + vv[e]) + cc[e], 0.0f)) : 0;
+        const float4 v0 = *reinterpret_cast<const float4*>(vr);
+        const float4 v1 = *reinterpret_cast<const float4*>(vr + 4);
         uint4 a;
-        a.x = h[0] | ((unsigned)h[1] << 16);
-        a.y = h[2] | ((unsigned)h[3] << 16);
-        a.z = h[4] | ((unsigned)h[5] << 16);
-        a.w = h[6] | ((unsigned)h[7] << 16);
+        a.x = bf16_pair(fmaxf((u0.x + v0.x) + c[0], 0.0f), fmaxf((u0.y + v0.y) + c[1], 0.0f));
+        a.y = bf16_pair(fmaxf((u0.z + v0.z) + c[2], 0.0f), fmaxf((u0.w + v0.w) + c[3], 0.0f));
+        a.z = bf16_pair(fmaxf((u1.x + v1.x) + c[4], 0.0f), fmaxf((u1.y + v1.y) + c[5], 0.0f));
+        a.w = bf16_pair(fmaxf((u1.z + v1.z) + c[6], 0.0f), fmaxf((u1.w + v1.w) + c[7], 0.0f));
+        if (f >= F) a = make_uint4(0, 0, 0, 0);
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), w, acc[t], 0, 0, 0);
       }
     }

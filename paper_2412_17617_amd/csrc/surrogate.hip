@@ -28,12 +28,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 64, TN = 64, TK = 16;
 
-__device__ __forceinline__ short to_bf16(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (short)(u >> 16);  // inf / nan pass through
-  u += 0x7fffu + ((u >> 16) & 1u);                                // round to nearest even
-  return (short)(u >> 16);
-}
+// FP32 -> BF16 bits, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950,
+// the conversion the fused inference kernels use too)
+__device__ __forceinline__ short to_bf16(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 
 // Problems whose A operand is cheaper with a per-row context computed once
 // per tile (Prob::Row, row(m), a_row(row, k)) instead of a(m, k) per element.
@@ -418,26 +415,29 @@ __global__ void k_candidate_maps(const uint8_t* base, const int* off, const int*
 
 // FoM (Eqs. 8-9 in closed form) of predicted S: terms on entries that are not
 // predicted are skipped.  pred: n x F x (3 n_entries), per entry ln|S| first.
+// A term's |S|^power with |S|^2 floored at 1e-30 is exp(power max(ln|S|,
+// ln(1e-30) / 2)).
 __global__ void k_pred_fom(const float* pred, int n, int F, int n_ent, const int* ent_i, const int* ent_j,
                            FomTable t, double* fom) {
-  // one wave per map: lanes take the frequencies in turn, then a fixed-order
-  // wave reduction
+  // one wave per map: terms in turn, lanes over the frequencies, then a
+  // fixed-order wave reduction
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (r >= n) return;  // whole waves leave together
+  const double floor_log = 0.5 * log(1e-30);
+  const float* pr = pred + (size_t)r * F * 3 * n_ent;
   double acc = 0.0;
-  for (int f = lane; f < F; f += 64) {
-    const int bnd = t.band[f];
-    if (bnd < 0) continue;
-    for (int q = 0; q < t.n_terms; ++q) {
-      if (t.terms[q].band != bnd) continue;
-      int e = -1;
-      for (int k = 0; k < n_ent; ++k)
-        if (ent_i[k] == t.terms[q].i && ent_j[k] == t.terms[q].j) e = k;
-      if (e < 0) continue;
-      const float* o = pred + ((size_t)r * F + f) * 3 * n_ent + 3 * e;  // (ln|S|, cos, sin)
-      const double m2 = fmax(exp(2.0 * (double)o[0]), 1e-30);
-      acc += t.term_fac[q] * pow(m2, 0.5 * t.terms[q].power);
+  for (int q = 0; q < t.n_terms; ++q) {
+    const pxd_fom_term tq = t.terms[q];
+    int e = -1;
+    for (int k = 0; k < n_ent; ++k)
+      if (ent_i[k] == tq.i && ent_j[k] == tq.j) e = k;
+    if (e < 0) continue;
+    const double fac = t.term_fac[q];
+    for (int f = lane; f < F; f += 64) {
+      if (t.band[f] != tq.band) continue;
+      const double ls = fmax((double)pr[(size_t)f * 3 * n_ent + 3 * e], floor_log);  // ln|S|
+      acc += fac * exp(tq.power * ls);
     }
   }
 #pragma unroll
