@@ -110,6 +110,10 @@ __device__ __forceinline__ void conv_layer(const InferLayer& L, const uint4* __r
       abase[m] = L.in_off + (4 * by + (r >> 2) + 1) * L.in_rs + (4 * bx + (r & 3) + 1) * L.in_cs +
                  (CSH >= 5 ? 8 * q : 0);
     }
+    float bcol[NB];  // the columns' biases, read before the products so the epilogue does not wait on them
+#pragma unroll
+    for (int n = 0; n < NB; ++n) bcol[n] = bias[16 * (n0 + n) + r];
+    __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the products
     f4 acc[MB][NB];
 #pragma unroll
     for (int m = 0; m < MB; ++m)
@@ -124,9 +128,9 @@ __device__ __forceinline__ void conv_layer(const InferLayer& L, const uint4* __r
           for (int n = 0; n < NB; ++n) bw[h][n] = as_bf16x8(wf[((size_t)(n0 + n) * KS + c * KH + h) * 64 + lane]);
         loaded = -1;
       }
-#pragma unroll
-      for (int h = 0; h < KH; ++h) {
-        const int s = c * KH + h;
+      // A fragments of step h + 1 are read while the MFMAs of step h run
+      uint4 acur[MB], anext[MB];
+      auto load_a = [&](uint4(&dst)[MB], int s) {
         // k = 32 s + 8 q .. + 7 is one tap and eight consecutive (padded) channels
         int toff;
         bool ok = true;
@@ -140,12 +144,20 @@ __device__ __forceinline__ void conv_layer(const InferLayer& L, const uint4* __r
           toff = (ty - 1) * L.in_rs + (tx - 1) * L.in_cs;
         }
 #pragma unroll
-        for (int m = 0; m < MB; ++m) {
-          const int addr = ok ? abase[m] + toff : zero_off;
-          const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4*>(lds + addr));
+        for (int m = 0; m < MB; ++m) dst[m] = *reinterpret_cast<const uint4*>(lds + (ok ? abase[m] + toff : zero_off));
+      };
+      load_a(acur, c * KH);
+#pragma unroll
+      for (int h = 0; h < KH; ++h) {
+        if (h + 1 < KH) load_a(anext, c * KH + h + 1);
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
 #pragma unroll
           for (int n = 0; n < NB; ++n)
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[h][n], acc[m][n], 0, 0, 0);
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(acur[m]), bw[h][n], acc[m][n], 0, 0, 0);
+        if (h + 1 < KH) {
+#pragma unroll
+          for (int m = 0; m < MB; ++m) acur[m] = anext[m];
         }
       }
     }
@@ -157,7 +169,7 @@ __device__ __forceinline__ void conv_layer(const InferLayer& L, const uint4* __r
 #pragma unroll
       for (int n = 0; n < NB; ++n) {
         const int col = 16 * (n0 + n) + r;
-        const float bc = bias[col];
+        const float bc = bcol[n];
         const f4 z = acc[m][n];
         const float v0 = fmaxf(z[0] + bc, 0.0f), v1 = fmaxf(z[1] + bc, 0.0f);
         const float v2 = fmaxf(z[2] + bc, 0.0f), v3 = fmaxf(z[3] + bc, 0.0f);
