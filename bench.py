@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 # dense MFMA peaks of the data type each form's trailing update issues
 PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3, "bf16x3": 2500.0}
+HBM_PEAK_GBPS = 8000.0
 PREC = {"fp64": 0, "mixed32": 1, "bf16": 2, "bf16x3": 4}
 
 
@@ -766,9 +767,27 @@ def main():
         for key in ("max_dS_vs_fp64_plain", "argmin_equal_fp64_plain", "fom_rel_dev_vs_fp64_plain",
                     "same_candidates_as_fp64_plain"):
             out["config"][key] = forms[chosen][key]
-    if chosen == "bf16x3":  # every real product is three BF16 MFMA products (hi hi, hi lo, lo hi)
-        out["roofline"]["mfma_issued_TFLOPs"] = 3.0 * upd["achieved_tflops"]
-        out["roofline"]["mfma_issued_frac"] = 3.0 * upd["achieved_tflops"] / PEAK_TFLOPS[chosen]
+    # The binding roof: the larger of the launch's compute floor (the MFMA flops it issues at the dense peak
+    # of their type; split-BF16 issues three BF16 products per real product: hi hi, hi lo, lo hi) and its
+    # memory floor (its algorithmic bytes at the HBM peak).
+    issued = 3.0 if chosen == "bf16x3" else 1.0
+    alg_gb = upd["gbyte_per_launch"]
+    floor_compute_us = issued * upd["gflop_per_launch"] / PEAK_TFLOPS[chosen] * 1e3
+    floor_memory_us = alg_gb / HBM_PEAK_GBPS * 1e6
+    ro = out["roofline"]
+    ro.update({"compute_floor_us": floor_compute_us, "memory_floor_us": floor_memory_us,
+               "mfma_issued_TFLOPs": issued * upd["achieved_tflops"],
+               "mfma_issued_frac": issued * upd["achieved_tflops"] / PEAK_TFLOPS[chosen],
+               "hbm_frac_algorithmic": upd["achieved_GBps"] / HBM_PEAK_GBPS})
+    if floor_memory_us > floor_compute_us:
+        ro.update({"bound": "hbm", "achieved": upd["achieved_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                   "frac": upd["achieved_GBps"] / HBM_PEAK_GBPS})
+        ro["basis"] = ("algorithmic bytes: the element size times (2 m n + kb m + kb n) per item and block column "
+                       "(C read and written once, L21 and U12 read once; m = N - Kend rows, n = trailing columns), "
+                       "summed over the "
+                       "step's trailing-update launches, / their summed duration (HIP event pair around each launch "
+                       "on the evaluation stream); HBM-bound because these bytes at 8 TB/s take longer than the "
+                       "issued MFMA flops at their dense peak")
     tr = measured_traffic(spec.name, upd["kernel"], head["top_k"] * spec.n_freq)
     if tr is not None:
         out["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
