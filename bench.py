@@ -565,7 +565,8 @@ def surrogate_leg(args, pxd, spec, torch):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    ok = bool(torch.isfinite(fp).all().item()) and int(top.min().item()) >= 0
+    fp_h, top_h = fp.cpu().numpy(), top.cpu().numpy()  # checked on the host: no other kernels in a profile
+    ok = bool(np.isfinite(fp_h).all()) and int(top_h.min()) >= 0
     generic = None
     if sur.inference == pxd.SUR_INFER_FUSED:
         # the same ranking through the training path's products, for comparison
@@ -579,8 +580,9 @@ def surrogate_leg(args, pxd, spec, torch):
         gen.rank(ev, t_base, t_off, t_cells, 32, fp_g, top_g, stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        dev_rel = float(((fp - fp_g).abs() / fp_g.abs()).max().item())
-        same_top = int(np.intersect1d(top.cpu().numpy(), top_g.cpu().numpy()).size)
+        fp_gh = fp_g.cpu().numpy()
+        dev_rel = float(np.max(np.abs(fp_h - fp_gh) / np.abs(fp_gh)))
+        same_top = int(np.intersect1d(top_h, top_g.cpu().numpy()).size)
         generic = {"ms": e0.elapsed_time(e1), "max_rel_fom_dev": dev_rel, "top32_overlap": same_top}
         gen.close()
     ch = (L, 32, 32, 64, 64)
@@ -597,6 +599,26 @@ def surrogate_leg(args, pxd, spec, torch):
             "precision": "bf16 products, fp32 accumulation", "weights": "random init (throughput only)",
             "flops_per_call": flops, "achieved_TFLOPs": flops / (ms / 1e3) / 1e12, "peak_TFLOPs": 2500.0,
             "top_valid": ok, "inference": path, "generic_products": generic}
+
+
+def run_legs(args, pxd, torch, legs):
+    """The extra legs named in `legs`, each an object of the JSON line."""
+    from synth import get_spec
+
+    extra = {}
+    if "stress24" in legs:
+        extra["stress24"] = batch_leg(args, pxd, torch, get_spec("stress24"), 64, ["fp64", "mixed32", "bf16x3"],
+                                      "stress24", lu_path=pxd.PATH_TILED)
+    if "batched20" in legs:
+        extra["batched20"] = batch_leg(args, pxd, torch, get_spec("batched20"), 800, ["fp64", "mixed32", "bf16x3"],
+                                       "batched20", tune=True, graph=True)
+    if "surrogate" in legs:
+        extra["surrogate"] = surrogate_leg(args, pxd, get_spec("stress24"), torch)
+    if "search24" in legs:
+        extra["search24"] = search_leg(args, pxd, torch)
+    if "lowrank" in legs:
+        extra["lowrank"] = lowrank_leg(args, pxd, get_spec("batched20"))
+    return extra
 
 
 def main():
@@ -617,6 +639,9 @@ def main():
     ap.add_argument("--search-steps", type=int, default=4, help="search24 leg: descent steps per method")
     ap.add_argument("--search-train-steps", type=int, default=1500, help="search24 leg: initial training steps")
     ap.add_argument("--search-finetune-steps", type=int, default=40, help="search24 leg: steps per new solve batch")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="run only the extra legs (no CPU baseline) and print their objects: a profiling aid, "
+                         "not the benchmark line")
     ap.add_argument("--legs", default="stress24,batched20,surrogate,lowrank",
                     help="comma list of extra legs (stress24, batched20, surrogate, lowrank; search24, the "
                          "surrogate-pruned against exhaustive search, about 8 minutes, is not in the default) or 'none'")
@@ -642,6 +667,9 @@ def main():
         del src, dst
         log("copy calibration: 1 GiB device-to-device copy done")
     spec = get_spec(args.workload)
+    if args.no_headline:
+        print(json.dumps(run_legs(args, pxd, torch, legs)), flush=True)
+        return
     log(f"workload {spec.name}: {spec.n_layers} layers {spec.nx}x{spec.ny}, {spec.n_freq} frequencies")
 
     # the CPU baseline's oracle fills (untimed) run beside the GPU legs
@@ -665,19 +693,7 @@ def main():
 
     modes = ["fp64"] + [m for m in args.forms.split(",") if m]
     head = headline_leg(args, pxd, torch, spec, modes)
-    extra = {}
-    if "stress24" in legs:
-        extra["stress24"] = batch_leg(args, pxd, torch, get_spec("stress24"), 64, ["fp64", "mixed32", "bf16x3"],
-                                      "stress24", lu_path=pxd.PATH_TILED)
-    if "batched20" in legs:
-        extra["batched20"] = batch_leg(args, pxd, torch, get_spec("batched20"), 800, ["fp64", "mixed32", "bf16x3"],
-                                       "batched20", tune=True, graph=True)
-    if "surrogate" in legs:
-        extra["surrogate"] = surrogate_leg(args, pxd, get_spec("stress24"), torch)
-    if "search24" in legs:
-        extra["search24"] = search_leg(args, pxd, torch)
-    if "lowrank" in legs:
-        extra["lowrank"] = lowrank_leg(args, pxd, get_spec("batched20"))
+    extra = run_legs(args, pxd, torch, legs)
 
     f64 = head["fp64"]
     forms = {}
