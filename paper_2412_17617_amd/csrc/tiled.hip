@@ -359,6 +359,21 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void k_tl_update(TlParams p, i
   fetch(K);
   const int wm = wid % WGM, wn = wid / WGM;
   const int rw = r0 + wm * WM, cw = c0 + wn * WN;
+  // complex64: C is read with the first stage's operands, so its latency is
+  // not paid after the products (complex128 has no registers to spare for it)
+  constexpr bool kEarlyC = sizeof(R) == 4;
+  T cv[SM][SN][4];
+  if constexpr (kEarlyC) {
+#pragma unroll
+    for (int a = 0; a < SM; ++a)
+#pragma unroll
+      for (int s = 0; s < SN; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
+          cv[a][s][i] = (r < t.N && col < cend) ? W[(size_t)r * ld + col] : T{0, 0};
+        }
+  }
   acc_t cr[SM][SN], ci[SM][SN];
 #pragma unroll
   for (int a = 0; a < SM; ++a)
@@ -429,7 +444,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void k_tl_update(TlParams p, i
       for (int i = 0; i < 4; ++i) {
         const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
         if (r < t.N && col < cend) {
-          const T v = W[(size_t)r * ld + col];
+          const T v = kEarlyC ? cv[a][s][i] : W[(size_t)r * ld + col];
           W[(size_t)r * ld + col] = T{v.x + cr[a][s][i], v.y + ci[a][s][i]};
         }
       }
@@ -437,26 +452,29 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void k_tl_update(TlParams p, i
 
 // Split-BF16 form of the complex64 trailing update (PXD_PREC_MIXED_BF16):
 // every operand x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), each
-// real product X Y as Xh Yh + Xh Yl + Xl Yh on the 16x16x16 BF16 MFMA with
+// real product X Y as Xh Yh + Xh Yl + Xl Yh on the 16x16x32 BF16 MFMA with
 // FP32 accumulation (the dropped Xl Yl is ~2^-16 relative).  BF16 keeps
-// FP32's exponent range, so no scaling is needed.  A stage is one 16-wide
-// k-chunk: L21 and U12 are split once when staged, into hi/lo planes of the
-// real and imaginary parts, L21 as [row][k] and U12 transposed as [col][k]
-// so that every fragment is four consecutive k of one row or column (one
-// 8-byte LDS read; row stride 24 keeps a wave's reads on distinct banks).
+// FP32's exponent range, so no scaling is needed.  A stage is one 32-deep
+// k-chunk: L21 and U12 are split once when staged (two k at a time, one
+// v_cvt_pk_bf16_f32 per pair and plane), into hi/lo planes of the real and
+// imaginary parts, L21 as [row][k] and U12 transposed as [col][k], so that
+// every fragment is eight consecutive k of one row or column: one 16-byte
+// LDS read, the 80-byte row stride putting sixteen lanes' reads on distinct
+// banks.  The next stage's operands are read from memory during this stage's
+// products.
 template <int TM, int TN, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K, int tiles_m, int tiles_n, int cb,
                                                                int ce) {
   using T = float2;
-  using HM = Half<PXD_HALF_BF16>;
-  using v4 = typename HM::v4;
   using MF = Mfma<float>;
-  constexpr int KC = 16, S16 = 24;
+  typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  constexpr int KC = 32, SW = 20;  // k per stage; LDS row stride in 32-bit words (two BF16 each)
   constexpr int WM = TM / 2, WN = TN / 2, SM = WM / 16, SN = WN / 16;
-  constexpr int NA = TM * KC / kThreads, NBV = KC * TN / kThreads;
-  static_assert(TM * KC % kThreads == 0 && KC * TN % kThreads == 0, "stage split");
-  // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
-  __shared__ __align__(16) short As[4][TM * S16], Bs[4][TN * S16];
+  constexpr int NA = TM * KC / 2 / kThreads, NBV = KC * TN / 2 / kThreads;  // k pairs staged per thread
+  static_assert(TM * KC / 2 % kThreads == 0 && KC * TN / 2 % kThreads == 0, "stage split");
+  // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo; word w of a row holds k = 2 w, 2 w + 1
+  __shared__ __align__(16) unsigned As[4][TM * SW], Bs[4][TN * SW];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
   const int total = gridDim.x * gridDim.y;
@@ -473,28 +491,47 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
   if (r0 >= t.N || c0 >= cend) return;
   const int ld = p.lay.ld;
   T* W = reinterpret_cast<T*>(p.ws + (size_t)b * p.slot_bytes);
-  T ra[NA], rb[NBV];
+  T ra[NA][2], rb[NBV][2];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
-      const int r = r0 + row, k = k0 + kk;
-      ra[i] = (r < t.N && k < Kend) ? W[(size_t)r * ld + k] : T{0, 0};
+      const int e = tid + kThreads * i, row = e / (KC / 2), kp = e - row * (KC / 2);
+      const int r = r0 + row, k = k0 + 2 * kp;
+      const bool in = r < t.N;
+      ra[i][0] = (in && k < Kend) ? W[(size_t)r * ld + k] : T{0, 0};
+      ra[i][1] = (in && k + 1 < Kend) ? W[(size_t)r * ld + k + 1] : T{0, 0};
     }
 #pragma unroll
     for (int i = 0; i < NBV; ++i) {
-      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
-      const int k = k0 + kr, cc = c0 + col;
-      rb[i] = (k < Kend && cc < cend) ? W[(size_t)k * ld + cc] : T{0, 0};
+      const int e = tid + kThreads * i, kp = e / TN, col = e - kp * TN;
+      const int k = k0 + 2 * kp, cc = c0 + col;
+      const bool in = cc < cend;
+      rb[i][0] = (in && k < Kend) ? W[(size_t)k * ld + cc] : T{0, 0};
+      rb[i][1] = (in && k + 1 < Kend) ? W[(size_t)(k + 1) * ld + cc] : T{0, 0};
     }
   };
-  auto split = [](float x, short& hi, short& lo) {
-    hi = HM::one(x);
-    lo = HM::one(x - __uint_as_float((unsigned)(unsigned short)hi << 16));
+  // (x0, x1) -> hi and lo words, round to nearest even
+  auto split2 = [](float x0, float x1, unsigned& hi, unsigned& lo) {
+    const bf2 h = {(__bf16)x0, (__bf16)x1};
+    hi = __builtin_bit_cast(unsigned, h);
+    const float r0 = x0 - __uint_as_float(hi << 16), r1 = x1 - __uint_as_float(hi & 0xffff0000u);
+    const bf2 l = {(__bf16)r0, (__bf16)r1};
+    lo = __builtin_bit_cast(unsigned, l);
   };
   fetch(K);
   const int wm = wid & 1, wn = wid >> 1;
   const int rw = r0 + wm * WM, cw = c0 + wn * WN;
+  // C is read with the first stage's operands, so its latency is not paid after the products
+  T cv[SM][SN][4];
+#pragma unroll
+  for (int a = 0; a < SM; ++a)
+#pragma unroll
+    for (int s = 0; s < SN; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
+        cv[a][s][i] = (r < t.N && col < cend) ? W[(size_t)r * ld + col] : T{0, 0};
+      }
   fx4 cr[SM][SN], ci[SM][SN];
 #pragma unroll
   for (int a = 0; a < SM; ++a)
@@ -509,45 +546,53 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
     __syncthreads();  // the previous stage is consumed
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int e = tid + kThreads * i, row = e / KC, kk = e - row * KC;
-      split(ra[i].x, As[0][row * S16 + kk], As[1][row * S16 + kk]);
-      split(ra[i].y, As[2][row * S16 + kk], As[3][row * S16 + kk]);
+      const int e = tid + kThreads * i, row = e / (KC / 2), kp = e - row * (KC / 2);
+      split2(ra[i][0].x, ra[i][1].x, As[0][row * SW + kp], As[1][row * SW + kp]);
+      split2(ra[i][0].y, ra[i][1].y, As[2][row * SW + kp], As[3][row * SW + kp]);
     }
 #pragma unroll
     for (int i = 0; i < NBV; ++i) {
-      const int e = tid + kThreads * i, kr = e / TN, col = e - kr * TN;
-      split(rb[i].x, Bs[0][col * S16 + kr], Bs[1][col * S16 + kr]);
-      split(rb[i].y, Bs[2][col * S16 + kr], Bs[3][col * S16 + kr]);
+      const int e = tid + kThreads * i, kp = e / TN, col = e - kp * TN;
+      split2(rb[i][0].x, rb[i][1].x, Bs[0][col * SW + kp], Bs[1][col * SW + kp]);
+      split2(rb[i][0].y, rb[i][1].y, Bs[2][col * SW + kp], Bs[3][col * SW + kp]);
     }
     __syncthreads();
     if (k0 + KC < Kend) fetch(k0 + KC);  // in flight during this stage's products
-    v4 fa[4][SM], fb[4][SN];  // fragments per plane
+    // lane (lk, l16): row (column) l16 of its sub-tile, k = 8 lk .. + 7
+    uint4 fa[4][SM], fb[4][SN];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma unroll
       for (int a = 0; a < SM; ++a)
-        fa[q][a] = *reinterpret_cast<const v4*>(&As[q][(wm * WM + 16 * a + l16) * S16 + 4 * lk]);
+        fa[q][a] = *reinterpret_cast<const uint4*>(&As[q][(wm * WM + 16 * a + l16) * SW + 4 * lk]);
 #pragma unroll
       for (int s = 0; s < SN; ++s)
-        fb[q][s] = *reinterpret_cast<const v4*>(&Bs[q][(wn * WN + 16 * s + l16) * S16 + 4 * lk]);
+        fb[q][s] = *reinterpret_cast<const uint4*>(&Bs[q][(wn * WN + 16 * s + l16) * SW + 4 * lk]);
     }
-    v4 nah[SM], nal[SM], naih[SM], nail[SM];  // -Ar and -Ai (sign bits flipped)
+    uint4 nah[SM], nal[SM], naih[SM], nail[SM];  // -Ar and -Ai (sign bits flipped)
+    auto neg = [](uint4 v) {
+      return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
+    };
 #pragma unroll
     for (int a = 0; a < SM; ++a) {
-      nah[a] = fa[0][a] ^ (short)0x8000;
-      nal[a] = fa[1][a] ^ (short)0x8000;
-      naih[a] = fa[2][a] ^ (short)0x8000;
-      nail[a] = fa[3][a] ^ (short)0x8000;
+      nah[a] = neg(fa[0][a]);
+      nal[a] = neg(fa[1][a]);
+      naih[a] = neg(fa[2][a]);
+      nail[a] = neg(fa[3][a]);
     }
+    auto mma = [](uint4 x, uint4 y, fx4 c) {
+      return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, x), __builtin_bit_cast(bf8, y), c, 0, 0,
+                                                     0);
+    };
     // Cr += (-Ar) Br + Ai Bi,  Ci += (-Ar) Bi + (-Ai) Br, each product in
     // three parts, issued part by part over all of the wave's tiles
 #define PXD_SPLIT3(ACC, XH, XL, YH, YL)                                                    \
   _Pragma("unroll") for (int a = 0; a < SM; ++a) _Pragma("unroll") for (int s = 0; s < SN; ++s) \
-      ACC[a][s] = HM::run(XH[a], YH[s], ACC[a][s]);                                      \
+      ACC[a][s] = mma(XH[a], YH[s], ACC[a][s]);                                          \
   _Pragma("unroll") for (int a = 0; a < SM; ++a) _Pragma("unroll") for (int s = 0; s < SN; ++s) \
-      ACC[a][s] = HM::run(XH[a], YL[s], ACC[a][s]);                                      \
+      ACC[a][s] = mma(XH[a], YL[s], ACC[a][s]);                                          \
   _Pragma("unroll") for (int a = 0; a < SM; ++a) _Pragma("unroll") for (int s = 0; s < SN; ++s) \
-      ACC[a][s] = HM::run(XL[a], YH[s], ACC[a][s]);
+      ACC[a][s] = mma(XL[a], YH[s], ACC[a][s]);
     PXD_SPLIT3(cr, nah, nal, fb[0], fb[1])
     PXD_SPLIT3(ci, nah, nal, fb[2], fb[3])
     PXD_SPLIT3(cr, fa[2], fa[3], fb[2], fb[3])
@@ -561,10 +606,8 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = rw + 16 * a + MF::row(lane, i), col = cw + 16 * s + l16;
-        if (r < t.N && col < cend) {
-          const T v = W[(size_t)r * ld + col];
-          W[(size_t)r * ld + col] = T{v.x + cr[a][s][i], v.y + ci[a][s][i]};
-        }
+        if (r < t.N && col < cend)
+          W[(size_t)r * ld + col] = T{cv[a][s][i].x + cr[a][s][i], cv[a][s][i].y + ci[a][s][i]};
       }
 }
 
@@ -988,9 +1031,9 @@ hipError_t tl_update(hipStream_t s, const TlParams& p, int K, int nmax, int cb, 
   const dim3 g(gx, p.B);
   if (split) {
     if (shape == 1)
-      hipLaunchKernelGGL((k_tl_update_bf16x3<64, 64, 3>), g, dim3(kThreads), 0, s, p, K, tiles_m, tiles_n, cb, ce);
+      hipLaunchKernelGGL((k_tl_update_bf16x3<64, 64, 2>), g, dim3(kThreads), 0, s, p, K, tiles_m, tiles_n, cb, ce);
     else
-      hipLaunchKernelGGL((k_tl_update_bf16x3<128, 64, 2>), g, dim3(kThreads), 0, s, p, K, tiles_m, tiles_n, cb, ce);
+      hipLaunchKernelGGL((k_tl_update_bf16x3<128, 64, 1>), g, dim3(kThreads), 0, s, p, K, tiles_m, tiles_n, cb, ce);
   } else if (p.mixed) {
     if (shape == 1) UpdShape<float>::launch<1>(s, g, p, K, tiles_m, tiles_n, cb, ce);
     else if (shape == 2) UpdShape<float>::launch<2>(s, g, p, K, tiles_m, tiles_n, cb, ce);
