@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
   constexpr int WM = TM / 2, WN = TN / 2, SM = WM / 16, SN = WN / 16;
   constexpr int NA = TM * KC / 2 / kThreads, NBV = KC * TN / 2 / kThreads;  // k pairs staged per thread
   static_assert(TM * KC / 2 % kThreads == 0 && KC * TN / 2 % kThreads == 0, "stage split");
-  // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo; word w of a row holds k = 2 w, 2 w + 1
+  // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo (of -L21 and of U12); word w of a row holds k = 2 w, 2 w + 1
   __shared__ __align__(16) unsigned As[4][TM * SW], Bs[4][TN * SW];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -547,8 +547,8 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + kThreads * i, row = e / (KC / 2), kp = e - row * (KC / 2);
-      split2(ra[i][0].x, ra[i][1].x, As[0][row * SW + kp], As[1][row * SW + kp]);
-      split2(ra[i][0].y, ra[i][1].y, As[2][row * SW + kp], As[3][row * SW + kp]);
+      split2(-ra[i][0].x, -ra[i][1].x, As[0][row * SW + kp], As[1][row * SW + kp]);  // -A (exact)
+      split2(-ra[i][0].y, -ra[i][1].y, As[2][row * SW + kp], As[3][row * SW + kp]);
     }
 #pragma unroll
     for (int i = 0; i < NBV; ++i) {
@@ -569,23 +569,20 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
       for (int s = 0; s < SN; ++s)
         fb[q][s] = *reinterpret_cast<const uint4*>(&Bs[q][(wn * WN + 16 * s + l16) * SW + 4 * lk]);
     }
-    uint4 nah[SM], nal[SM], naih[SM], nail[SM];  // -Ar and -Ai (sign bits flipped)
-    auto neg = [](uint4 v) {
-      return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
-    };
+    uint4 nbh[SN], nbl[SN];  // -Bi (sign bits flipped)
 #pragma unroll
-    for (int a = 0; a < SM; ++a) {
-      nah[a] = neg(fa[0][a]);
-      nal[a] = neg(fa[1][a]);
-      naih[a] = neg(fa[2][a]);
-      nail[a] = neg(fa[3][a]);
+    for (int s = 0; s < SN; ++s) {
+      nbh[s] = make_uint4(fb[2][s].x ^ 0x80008000u, fb[2][s].y ^ 0x80008000u, fb[2][s].z ^ 0x80008000u,
+                          fb[2][s].w ^ 0x80008000u);
+      nbl[s] = make_uint4(fb[3][s].x ^ 0x80008000u, fb[3][s].y ^ 0x80008000u, fb[3][s].z ^ 0x80008000u,
+                          fb[3][s].w ^ 0x80008000u);
     }
     auto mma = [](uint4 x, uint4 y, fx4 c) {
       return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, x), __builtin_bit_cast(bf8, y), c, 0, 0,
                                                      0);
     };
-    // Cr += (-Ar) Br + Ai Bi,  Ci += (-Ar) Bi + (-Ai) Br, each product in
-    // three parts, issued part by part over all of the wave's tiles
+    // with -A staged: Cr += (-Ar) Br + (-Ai)(-Bi),  Ci += (-Ar) Bi + (-Ai) Br,
+    // each product in three parts, issued part by part over all of the wave's tiles
 #define PXD_SPLIT3(ACC, XH, XL, YH, YL)                                                    \
   _Pragma("unroll") for (int a = 0; a < SM; ++a) _Pragma("unroll") for (int s = 0; s < SN; ++s) \
       ACC[a][s] = mma(XH[a], YH[s], ACC[a][s]);                                          \
@@ -593,10 +590,10 @@ __global__ __launch_bounds__(256, OCC) void k_tl_update_bf16x3(TlParams p, int K
       ACC[a][s] = mma(XH[a], YL[s], ACC[a][s]);                                          \
   _Pragma("unroll") for (int a = 0; a < SM; ++a) _Pragma("unroll") for (int s = 0; s < SN; ++s) \
       ACC[a][s] = mma(XL[a], YH[s], ACC[a][s]);
-    PXD_SPLIT3(cr, nah, nal, fb[0], fb[1])
-    PXD_SPLIT3(ci, nah, nal, fb[2], fb[3])
-    PXD_SPLIT3(cr, fa[2], fa[3], fb[2], fb[3])
-    PXD_SPLIT3(ci, naih, nail, fb[0], fb[1])
+    PXD_SPLIT3(cr, fa[0], fa[1], fb[0], fb[1])
+    PXD_SPLIT3(ci, fa[0], fa[1], fb[2], fb[3])
+    PXD_SPLIT3(cr, fa[2], fa[3], nbh, nbl)
+    PXD_SPLIT3(ci, fa[2], fa[3], fb[0], fb[1])
 #undef PXD_SPLIT3
   }
 #pragma unroll
