@@ -797,109 +797,85 @@ __device__ __forceinline__ int port_solve_and_s(const double2* __restrict__ W, i
 
 // ------------------------------------------------------------------ mixed precision
 
-// out[jr] -= sum_j row[j] y[j * P + jr] for j < kb (kb <= NB), jr < P: the
-// row segment is read with unrolled 16-byte loads issued back to back.
-__device__ __forceinline__ void rows_update(const float2* __restrict__ row, int kb, const float2* y, float2* out,
-                                            int P) {
-  float4 seg[NB / 2];
-  const float4* r4 = reinterpret_cast<const float4*>(row);
-  const bool aligned = (reinterpret_cast<uintptr_t>(row) & 15) == 0;
+// b[r] -= sum over j < kb of W[r][k + j] y[j] for the rows r_lo <= r < r_hi,
+// all waves of the workgroup: eight lanes per row, each lane four
+// consecutive entries (contiguous 16-byte loads across the row), eight row
+// groups per wave in flight (a lone workgroup is bound by load latency), the
+// eight partial sums reduced over the row's lanes and added to b once.
+// y (kb x P) and b may be in LDS.
+__device__ __forceinline__ void rows_update_block(const float2* __restrict__ W, int ld, int k, int kb, int r_lo,
+                                                  int r_hi, const float2* y, float2* b, int P) {
+  constexpr int RG = 8;  // row groups per wave per step
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int sub = lane >> 3, l8 = lane & 7, j0 = 4 * l8;
+  const bool vec = ((ld & 1) == 0) && j0 + 3 < kb;  // 16-byte aligned and inside the block
+  float2 yv[4][4];
 #pragma unroll
-  for (int q = 0; q < NB / 2; ++q) {
-    if (2 * q + 1 < kb && aligned) {
-      seg[q] = r4[q];
-    } else {
-      const float2 lo = (2 * q < kb) ? row[2 * q] : float2{0, 0};
-      const float2 hi = (2 * q + 1 < kb) ? row[2 * q + 1] : float2{0, 0};
-      seg[q] = float4{lo.x, lo.y, hi.x, hi.y};
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int jr = 0; jr < 4; ++jr) yv[u][jr] = (jr < P && j0 + u < kb) ? y[(j0 + u) * P + jr] : float2{0, 0};
+  for (int r0 = r_lo + 8 * RG * wid; r0 < r_hi; r0 += 8 * RG * kWaves) {
+    float2 w[RG][4];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const int r = r0 + 8 * g + sub;
+      const float2* row = W + (size_t)r * ld + k + j0;
+      if (r < r_hi && vec) {
+        const float4 a = reinterpret_cast<const float4*>(row)[0], c = reinterpret_cast<const float4*>(row)[1];
+        w[g][0] = float2{a.x, a.y}, w[g][1] = float2{a.z, a.w}, w[g][2] = float2{c.x, c.y}, w[g][3] = float2{c.z, c.w};
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[g][u] = (r < r_hi && j0 + u < kb) ? row[u] : float2{0, 0};
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const int r = r0 + 8 * g + sub;
+      float2 acc[4] = {};  // the products are summed apart from b (one rounding into it)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int jr = 0; jr < 4; ++jr)
+          if (jr < P) acc[jr] = cfms(acc[jr], w[g][u], yv[u][jr]);
+#pragma unroll
+      for (int jr = 0; jr < 4; ++jr) {
+        if (jr >= P) continue;
+#pragma unroll
+        for (int off = 4; off >= 1; off >>= 1) {
+          acc[jr].x += __shfl_xor(acc[jr].x, off, 64);
+          acc[jr].y += __shfl_xor(acc[jr].y, off, 64);
+        }
+        if (l8 == 0 && r < r_hi) b[(size_t)r * P + jr] = float2{b[(size_t)r * P + jr].x + acc[jr].x,
+                                                                 b[(size_t)r * P + jr].y + acc[jr].y};
+      }
     }
   }
-  float2 acc[4] = {};  // the products are summed apart from out (one rounding into it)
-#pragma unroll
-  for (int q = 0; q < NB / 2; ++q) {
-    const float2 l0 = float2{seg[q].x, seg[q].y}, l1 = float2{seg[q].z, seg[q].w};
-#pragma unroll
-    for (int jr = 0; jr < 4; ++jr)
-      if (jr < P) {
-        if (2 * q < kb) acc[jr] = cfms(acc[jr], l0, y[(2 * q) * P + jr]);
-        if (2 * q + 1 < kb) acc[jr] = cfms(acc[jr], l1, y[(2 * q + 1) * P + jr]);
-      }
-  }
-#pragma unroll
-  for (int jr = 0; jr < 4; ++jr)
-    if (jr < P) out[jr] = float2{out[jr].x + acc[jr].x, out[jr].y + acc[jr].y};
 }
 
-// rows_update for two rows at once: both rows' segments are loaded before
-// either is used, so twice the bytes are in flight per thread.
-__device__ __forceinline__ void rows_update2(const float2* __restrict__ rowA, const float2* __restrict__ rowB,
-                                             int kb, const float2* y, float2* outA, float2* outB, int P) {
-  float4 sa[NB / 2], sb[NB / 2];
-  const float4* a4 = reinterpret_cast<const float4*>(rowA);
-  const float4* b4 = reinterpret_cast<const float4*>(rowB);
-  const bool aligned = ((reinterpret_cast<uintptr_t>(rowA) | reinterpret_cast<uintptr_t>(rowB)) & 15) == 0;
-#pragma unroll
-  for (int q = 0; q < NB / 2; ++q) {
-    if (2 * q + 1 < kb && aligned) {
-      sa[q] = a4[q];
-      sb[q] = b4[q];
-    } else {
-      const float2 al = (2 * q < kb) ? rowA[2 * q] : float2{0, 0}, ah = (2 * q + 1 < kb) ? rowA[2 * q + 1] : float2{0, 0};
-      const float2 bl = (2 * q < kb) ? rowB[2 * q] : float2{0, 0}, bh = (2 * q + 1 < kb) ? rowB[2 * q + 1] : float2{0, 0};
-      sa[q] = float4{al.x, al.y, ah.x, ah.y};
-      sb[q] = float4{bl.x, bl.y, bh.x, bh.y};
-    }
-  }
-  float2 accA[4] = {}, accB[4] = {};  // summed apart from outA, outB
-#pragma unroll
-  for (int q = 0; q < NB / 2; ++q) {
-    const float2 a0 = float2{sa[q].x, sa[q].y}, a1 = float2{sa[q].z, sa[q].w};
-    const float2 b0 = float2{sb[q].x, sb[q].y}, b1 = float2{sb[q].z, sb[q].w};
-#pragma unroll
-    for (int jr = 0; jr < 4; ++jr)
-      if (jr < P) {
-        if (2 * q < kb) {
-          const float2 yv = y[(2 * q) * P + jr];
-          accA[jr] = cfms(accA[jr], a0, yv);
-          accB[jr] = cfms(accB[jr], b0, yv);
-        }
-        if (2 * q + 1 < kb) {
-          const float2 yv = y[(2 * q + 1) * P + jr];
-          accA[jr] = cfms(accA[jr], a1, yv);
-          accB[jr] = cfms(accB[jr], b1, yv);
-        }
-      }
-  }
-#pragma unroll
-  for (int jr = 0; jr < 4; ++jr)
-    if (jr < P) {
-      outA[jr] = float2{outA[jr].x + accA[jr].x, outA[jr].y + accA[jr].y};
-      outB[jr] = float2{outB[jr].x + accB[jr].x, outB[jr].y + accB[jr].y};
-    }
-}
+constexpr int kTlKbMaxSolve = 128;  // widest block column whose interchanges lu_solve_c64 replays
 
-// Solve (L U) x = P b in complex64 for the P right-hand sides held in LDS
-// (b[row * P + j]), using the factor in W (unit-lower L below the diagonal,
-// U on and above) and the pivots of a factorisation in block columns of
-// kblock (a multiple of NB).  Interchanges were applied only to a block
-// column and the columns right of it during the factorisation, so they are
-// replayed block column by block column between the eliminations.
 __device__ __forceinline__ void lu_solve_c64(const float2* __restrict__ W, int ld, int N, const int* __restrict__ piv,
                                              float2* b, int P, int kblock = KB_MIXED) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ int s_piv[kTlKbMaxSolve];  // the block column's pivots, read in parallel before the serial swaps
   // forward: b <- L^-1 P b; a block column's interchanges all precede its
   // eliminations (its L is stored in the block's final row order)
   for (int k = 0; k < N; k += NB) {
     const int kb = min(NB, N - k);
-    if (tid < P && k % kblock == 0)
-      for (int i = 0; i < min(kblock, N - k); ++i) {
-        const int r = k + i, q = piv[r];
-        if (q != r) {
-          const float2 t = b[r * P + tid];
-          b[r * P + tid] = b[q * P + tid];
-          b[q * P + tid] = t;
+    if (k % kblock == 0) {
+      const int nk = min(kblock, N - k);
+      for (int i = tid; i < nk; i += kThreads) s_piv[i] = piv[k + i];
+      __syncthreads();
+      if (tid < P)
+        for (int i = 0; i < nk; ++i) {
+          const int r = k + i, q = s_piv[i];
+          if (q != r) {
+            const float2 t = b[r * P + tid];
+            b[r * P + tid] = b[q * P + tid];
+            b[q * P + tid] = t;
+          }
         }
-      }
+    }
     __syncthreads();
     if (wid == 0) {
       float2 l[NB];
@@ -917,13 +893,7 @@ __device__ __forceinline__ void lu_solve_c64(const float2* __restrict__ W, int l
       }
     }
     __syncthreads();
-    for (int r = k + kb + tid; r < N; r += 2 * kThreads) {  // two rows per step: both rows' loads in flight
-      if (r + kThreads < N)
-        rows_update2(W + (size_t)r * ld + k, W + (size_t)(r + kThreads) * ld + k, kb, b + (size_t)k * P,
-                     b + (size_t)r * P, b + (size_t)(r + kThreads) * P, P);
-      else
-        rows_update(W + (size_t)r * ld + k, kb, b + (size_t)k * P, b + (size_t)r * P, P);
-    }
+    rows_update_block(W, ld, k, kb, k + kb, N, b + (size_t)k * P, b, P);
     __syncthreads();
   }
   // backward: b <- U^-1 b
@@ -956,13 +926,7 @@ __device__ __forceinline__ void lu_solve_c64(const float2* __restrict__ W, int l
       }
     }
     __syncthreads();
-    for (int r = tid; r < k; r += 2 * kThreads) {
-      if (r + kThreads < k)
-        rows_update2(W + (size_t)r * ld + k, W + (size_t)(r + kThreads) * ld + k, kb, b + (size_t)k * P,
-                     b + (size_t)r * P, b + (size_t)(r + kThreads) * P, P);
-      else
-        rows_update(W + (size_t)r * ld + k, kb, b + (size_t)k * P, b + (size_t)r * P, P);
-    }
+    rows_update_block(W, ld, k, kb, 0, k, b + (size_t)k * P, b, P);
     __syncthreads();
   }
 }
