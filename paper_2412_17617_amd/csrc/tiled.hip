@@ -661,7 +661,7 @@ __device__ __forceinline__ double* ir_mprev(int* aux) { return reinterpret_cast<
 // x0 = (LU)^-1 V for one item, into its slot and into its group's X block.
 __global__ __launch_bounds__(256) void k_ir_init(TlParams p, IrParams q, int nmax) {
   extern __shared__ char dyn[];
-  float2* bvec = reinterpret_cast<float2*>(dyn + ((size_t)nmax * 4 + 15) / 16 * 16);
+  float2* bvec = reinterpret_cast<float2*>(dyn);  // ir_lds(nmax, P): the right-hand sides only
   const int b = blockIdx.x, tid = threadIdx.x;
   const TlItem t = tl_item(p, b);
   char* slot = p.ws + (size_t)b * p.slot_bytes;
@@ -768,8 +768,7 @@ __global__ __launch_bounds__(256) void k_ir_residual(TlParams p, IrParams q) {
 // solve of the correction, x += d, and x back into X.
 __global__ __launch_bounds__(256) void k_ir_step(TlParams p, IrParams q, int nmax) {
   extern __shared__ char dyn[];
-  int* sP = reinterpret_cast<int*>(dyn);  // U positions of the item's rows
-  float2* bvec = reinterpret_cast<float2*>(dyn + ((size_t)nmax * 4 + 15) / 16 * 16);
+  float2* bvec = reinterpret_cast<float2*>(dyn);  // ir_lds(nmax, P): the right-hand sides only
   __shared__ int s_v;
   __shared__ double s_ds[16], s_sabs[16];
   __shared__ double2 s_delta[16], s_part[kWaves * 16];
@@ -785,12 +784,10 @@ __global__ __launch_bounds__(256) void k_ir_step(TlParams p, IrParams q, int nma
   const int g = q.item_grp[b], col = q.item_col[b];
   const double2* R = q.R + (size_t)g * q.U * q.ldx;
   double2* X = q.X + (size_t)g * q.U * q.ldx;
-  const int* I = p.Ilist + (size_t)t.c * p.M;
-  for (int i = tid; i < N; i += kThreads) sP[i] = q.upos[I[i]];
-  __syncthreads();
+  const int* I = p.Ilist + (size_t)t.c * p.M;  // row i of the item is row upos[I[i]] of U
   for (int e = tid; e < N * P; e += kThreads) {
     const int i = e / P, jr = e - i * P;
-    const double2 zx = R[(size_t)sP[i] * q.ldx + col + jr];
+    const double2 zx = R[(size_t)q.upos[I[i]] * q.ldx + col + jr];
     double2 r = double2{-zx.x, -zx.y};
     const int pi = i - (N - P);  // port index of this row, if it is a port row
     if (pi >= 0) {
@@ -871,7 +868,7 @@ __global__ __launch_bounds__(256) void k_ir_step(TlParams p, IrParams q, int nma
     xv.x += d.x;
     xv.y += d.y;
     x[e] = xv;
-    X[(size_t)sP[i] * q.ldx + col + jr] = xv;
+    X[(size_t)q.upos[I[i]] * q.ldx + col + jr] = xv;
     if (i >= N - P) s_ds[(i - (N - P)) * P + jr] = 2.0 * p.z0 * p.port_len[i - (N - P)] * sqrt(d.x * d.x + d.y * d.y);
   }
   __syncthreads();
@@ -1056,8 +1053,12 @@ hipError_t tl_prepare(const TlParams& p, int nmax) {
   return hipSuccess;
 }
 
+// LDS of the lock-step refinement kernels: the right-hand sides (nmax x P
+// complex64), small enough at the 32x32x3 sizes for two workgroups per CU
+static size_t ir_lds(int nmax, int P) { return (size_t)nmax * P * sizeof(float2); }
+
 hipError_t tl_ir_init(hipStream_t s, const TlParams& p, const IrParams& q, int nmax) {
-  hipLaunchKernelGGL(k_ir_init, dim3(p.B), dim3(kThreads), eval_mixed_lds(nmax, p.P), s, p, q, nmax);
+  hipLaunchKernelGGL(k_ir_init, dim3(p.B), dim3(kThreads), ir_lds(nmax, p.P), s, p, q, nmax);
   return hipGetLastError();
 }
 
@@ -1069,7 +1070,7 @@ hipError_t tl_ir_residual(hipStream_t s, const TlParams& p, const IrParams& q, i
 }
 
 hipError_t tl_ir_step(hipStream_t s, const TlParams& p, const IrParams& q, int nmax) {
-  hipLaunchKernelGGL(k_ir_step, dim3(p.B), dim3(kThreads), eval_mixed_lds(nmax, p.P), s, p, q, nmax);
+  hipLaunchKernelGGL(k_ir_step, dim3(p.B), dim3(kThreads), ir_lds(nmax, p.P), s, p, q, nmax);
   return hipGetLastError();
 }
 
