@@ -29,6 +29,10 @@
 #include "kernels.hpp"
 #include "lu_device.hpp"
 
+// lu_solve_c64 replays a block column's interchanges from a table of this size
+static_assert(pxd::kTlKbMax <= pxd::kTlKbMaxSolve && pxd::KB_MIXED <= pxd::kTlKbMaxSolve,
+              "block columns wider than the solve's pivot table");
+
 namespace pxd {
 
 // ------------------------------------------------------------------ expand
