@@ -59,6 +59,19 @@ def kernel_name(path, mode):
     return "k_eval_plain" if mode == "fp64" else "k_eval_mixed"
 
 
+def binding_roof(form, gflop_per_launch, gbyte_per_launch):
+    """The roof that binds one trailing-update launch: the larger of its
+    compute floor (the MFMA flops it issues at the dense peak of their type;
+    split-BF16 issues three BF16 products per real product: hi hi, hi lo,
+    lo hi) and its memory floor (its algorithmic bytes at the HBM peak).
+    Returns (bound, compute floor us, memory floor us, products issued per
+    real product)."""
+    issued = 3.0 if form == "bf16x3" else 1.0
+    compute_us = issued * gflop_per_launch / PEAK_TFLOPS[form] * 1e3
+    memory_us = gbyte_per_launch / HBM_PEAK_GBPS * 1e6
+    return ("hbm" if memory_us > compute_us else "mfma"), compute_us, memory_us, issued
+
+
 def measured_traffic(workload, kernel, items):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is none for
@@ -783,19 +796,14 @@ def main():
         for key in ("max_dS_vs_fp64_plain", "argmin_equal_fp64_plain", "fom_rel_dev_vs_fp64_plain",
                     "same_candidates_as_fp64_plain"):
             out["config"][key] = forms[chosen][key]
-    # The binding roof: the larger of the launch's compute floor (the MFMA flops it issues at the dense peak
-    # of their type; split-BF16 issues three BF16 products per real product: hi hi, hi lo, lo hi) and its
-    # memory floor (its algorithmic bytes at the HBM peak).
-    issued = 3.0 if chosen == "bf16x3" else 1.0
-    alg_gb = upd["gbyte_per_launch"]
-    floor_compute_us = issued * upd["gflop_per_launch"] / PEAK_TFLOPS[chosen] * 1e3
-    floor_memory_us = alg_gb / HBM_PEAK_GBPS * 1e6
+    bound, floor_compute_us, floor_memory_us, issued = binding_roof(chosen, upd["gflop_per_launch"],
+                                                                    upd["gbyte_per_launch"])
     ro = out["roofline"]
     ro.update({"compute_floor_us": floor_compute_us, "memory_floor_us": floor_memory_us,
                "mfma_issued_TFLOPs": issued * upd["achieved_tflops"],
                "mfma_issued_frac": issued * upd["achieved_tflops"] / PEAK_TFLOPS[chosen],
                "hbm_frac_algorithmic": upd["achieved_GBps"] / HBM_PEAK_GBPS})
-    if floor_memory_us > floor_compute_us:
+    if bound == "hbm":
         ro.update({"bound": "hbm", "achieved": upd["achieved_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                    "frac": upd["achieved_GBps"] / HBM_PEAK_GBPS})
         ro["basis"] = ("algorithmic bytes: the element size times (2 m n + kb m + kb n) per item and block column "

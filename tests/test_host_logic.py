@@ -175,3 +175,23 @@ def test_refine_verdict_needs_rho_below_09():
 def test_refine_verdict_rejects_bad_arguments():
     with pytest.raises(pxd.PxdError):
         pxd.refine_verdict(0, 10, 1.0, 1.0, 1.0)
+
+
+def test_bench_binding_roof():
+    """The bench's roofline names the roof the dominant launch's floors
+    select: at 56 flop per algorithmic byte (the 32x32x3 update, 572 GFLOP on
+    10.2 GB per launch) the split-BF16 update (three BF16 products per real
+    product at 2.5 PFLOP/s: 0.69 ms) is bound by the 1.27 ms its bytes need
+    at 8 TB/s; the complex64 (FP32 MFMA, 3.64 ms) and FP64 (complex128
+    bytes, 7.28 ms against 2.58 ms) updates by the MFMA rate."""
+    import bench
+
+    bound, comp, mem, issued = bench.binding_roof("bf16x3", 572.38, 10.19)
+    assert bound == "hbm" and issued == 3.0
+    assert comp == pytest.approx(3 * 572.38 / 2500.0 * 1e3) and mem == pytest.approx(10.19 / 8000.0 * 1e6)
+    bound, comp, mem, _ = bench.binding_roof("mixed32", 572.38, 10.18)
+    assert bound == "mfma" and comp == pytest.approx(572.38 / 157.3 * 1e3)
+    bound, comp, mem, _ = bench.binding_roof("fp64", 572.38, 20.64)
+    assert bound == "mfma" and comp > mem
+    # the same launch with four times the bytes would be HBM-bound in complex64 too
+    assert bench.binding_roof("mixed32", 572.38, 4 * 10.18)[0] == "hbm"
