@@ -99,6 +99,11 @@ struct pxd_ctx {
   // two events that order it against the call's stream
   hipStream_t aux = nullptr;
   hipEvent_t la_ev[2] = {};
+  // tiled path: the lock-step refinement of a chunk runs on `ref` beside the
+  // next chunk's factorisation (the chunks alternate between two halves of
+  // the workspace); pp_ev[h] = chunk factored, pp_ev[2 + h] = chunk refined
+  hipStream_t ref = nullptr;
+  hipEvent_t pp_ev[4] = {};
   // tiled path, when profiling is on: one event pair per trailing-update launch
   bool profile = false;
   std::vector<hipEvent_t> upd_ev;
@@ -271,6 +276,10 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
     return ctx->fail(PXD_ENOMEM, "tiled LU: one item's workspace (" + std::to_string(lay_all.bytes) +
                                      " bytes) exceeds the workspace cap (" + std::to_string(cap) + " bytes)");
   HIPCHK(ctx, b.ws.ensure(lay_all.bytes * (size_t)bmax));
+  // with the lock-step refinement, chunks of half the workspace: chunk c
+  // factors in half c % 2 while chunk c - 1 refines in the other half
+  const bool lockstep = U > 0 && mixed && !fallback_mode;
+  const int cb = lockstep && bmax >= 2 && n > bmax / 2 ? bmax / 2 : bmax;
   const int kb = tile_kb(ctx, nmax_all);
   pxd::TlParams tp{};
   tp.Z128 = ctx->Z128.as<double2>();
@@ -303,12 +312,12 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
   };
   std::vector<ChunkIr> cir;
   int ldx = 0, n_grp_max = 0;
-  if (U > 0 && mixed && !fallback_mode) {
+  if (lockstep) {
     std::vector<int>& tab = ctx->h_ir;
     tab.clear();
     std::vector<int> gid(ctx->F, -1);
-    for (int i0 = 0; i0 < n; i0 += bmax) {
-      const int B = std::min(bmax, n - i0);
+    for (int i0 = 0; i0 < n; i0 += cb) {
+      const int B = std::min(cb, n - i0);
       std::vector<int> gf, gn;
       ChunkIr c{tab.size(), 0, 0};
       tab.resize(tab.size() + 2 * (size_t)B);
@@ -343,14 +352,20 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
       HIPCHK(ctx, ctx->ir_xr.ensure(xr));
     }
   }
-  for (int i0 = 0, chunk = 0; i0 < n; i0 += bmax, ++chunk) {
-    const int B = std::min(bmax, n - i0);
+  const bool pipelined = !cir.empty() && cb < bmax;
+  int n_chunks = 0;
+  for (int i0 = 0, chunk = 0; i0 < n; i0 += cb, ++chunk, ++n_chunks) {
+    const int B = std::min(cb, n - i0);
+    const int h = chunk & 1;  // workspace half (pipelined)
     int nmax = 0;
     for (int i = i0; i < i0 + B; ++i) nmax = std::max(nmax, ctx->hNc[list[i] / F]);
     tp.items = d_list + i0;
     tp.B = B;
     tp.lay = pxd::tl_layout(nmax, P, mixed);
     tp.slot_bytes = tp.lay.bytes;
+    tp.ws = b.ws.as<char>() + (pipelined ? (size_t)h * cb * lay_all.bytes : 0);
+    // the half's slots are free once the chunk two before has refined
+    if (pipelined && chunk >= 2) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->pp_ev[2 + h], 0));
     const int ne_max = mixed ? nmax : nmax - P;
     HIPCHK(ctx, pxd::tl_gather(s, tp, nmax));
     if (ne_max > 0) {
@@ -378,6 +393,12 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
       }
     }
     if (!cir.empty()) {
+      hipStream_t rs = s;
+      if (pipelined) {  // refine beside the next chunk's factorisation
+        HIPCHK(ctx, hipEventRecord(ctx->pp_ev[h], s));
+        HIPCHK(ctx, hipStreamWaitEvent(ctx->ref, ctx->pp_ev[h], 0));
+        rs = ctx->ref;
+      }
       const ChunkIr& c = cir[chunk];
       int* tab = ctx->ir_tab.as<int>() + c.off;
       pxd::IrParams q{};
@@ -393,16 +414,19 @@ int run_tiled(pxd_ctx* ctx, EvalBufs& b, hipStream_t s, const int* d_list, const
       q.grp_ncol = tab + 2 * B + c.n_grp;
       q.grp_active = tab + 2 * B + 2 * c.n_grp;
       q.n_grp = c.n_grp;
-      HIPCHK(ctx, pxd::launch_zero_c128(s, q.X, (size_t)c.n_grp * U * ldx));
-      HIPCHK(ctx, pxd::tl_ir_init(s, tp, q, nmax));
+      HIPCHK(ctx, pxd::launch_zero_c128(rs, q.X, (size_t)c.n_grp * U * ldx));
+      HIPCHK(ctx, pxd::tl_ir_init(rs, tp, q, nmax));
       for (int it = 0; it < std::max(1, ctx->opt.ir_max_iter); ++it) {
-        HIPCHK(ctx, pxd::tl_ir_residual(s, tp, q, c.max_ncol));
-        HIPCHK(ctx, pxd::tl_ir_step(s, tp, q, nmax));
+        HIPCHK(ctx, pxd::tl_ir_residual(rs, tp, q, c.max_ncol));
+        HIPCHK(ctx, pxd::tl_ir_step(rs, tp, q, nmax));
       }
+      if (pipelined) HIPCHK(ctx, hipEventRecord(ctx->pp_ev[2 + h], rs));
     } else {
       HIPCHK(ctx, pxd::tl_finish(s, tp, nmax));
     }
   }
+  if (pipelined)  // everything after this call runs on s
+    for (int h = 0; h < 2 && h < n_chunks; ++h) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->pp_ev[2 + h], 0));
   return PXD_OK;
 }
 
@@ -912,7 +936,13 @@ int pxd_create(const pxd_options* opt, pxd_ctx** out) {
       pxd_destroy(ctx);
       return pxd::set_thread_error(PXD_EDEVICE, "event creation failed");
     }
-  if ((e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking)) != hipSuccess) {  // default priority
+  for (auto& ev : ctx->pp_ev)
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+      pxd_destroy(ctx);
+      return pxd::set_thread_error(PXD_EDEVICE, "event creation failed");
+    }
+  if ((e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking)) != hipSuccess ||  // default priorities
+      (e = hipStreamCreateWithFlags(&ctx->ref, hipStreamNonBlocking)) != hipSuccess) {
     pxd_destroy(ctx);
     return pxd::set_thread_error(PXD_EDEVICE, "stream creation failed");
   }
@@ -943,10 +973,13 @@ void pxd_destroy(pxd_ctx* ctx) {
   for (auto& ev : ctx->upd_ev) (void)hipEventDestroy(ev);
   for (auto& ev : ctx->la_ev)
     if (ev) (void)hipEventDestroy(ev);
-  if (ctx->aux) {
-    (void)hipStreamSynchronize(ctx->aux);
-    (void)hipStreamDestroy(ctx->aux);
-  }
+  for (auto& ev : ctx->pp_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  for (hipStream_t* st : {&ctx->aux, &ctx->ref})
+    if (*st) {
+      (void)hipStreamSynchronize(*st);
+      (void)hipStreamDestroy(*st);
+    }
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
