@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import efie, geometry
+from fill_common import near_series_switch_freqs
 from synth import get_spec
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -54,6 +55,24 @@ def test_host_fill_matches_oracle_fill(name):
     pb = pxd.Problem.from_spec(spec)
     st = geometry.build_structure(spec)
     freqs = spec.freqs[[0, -1]]
+    Z = pb.fill(freqs, n_threads=4)
+    Zo = np.stack([efie.fill(st, f) for f in freqs])
+    assert np.array_equal(Z, np.transpose(Z, (0, 2, 1)))
+    assert np.abs(Z - Zo).max() <= 1e-12 * np.abs(Zo).max()
+
+
+@pytest.mark.parametrize("name", ["plain8", "tiny4x2"])
+def test_host_fill_across_the_near_series_switch(name):
+    """The band-edge cases above evaluate every near pair's smooth remainder
+    by the exponential; at these frequencies half of the near pairs' point
+    distances (then all of them) take the series instead.  At the higher one
+    a wrong second- or third-order coefficient moves Z by 6e-12 of max |Z|
+    or more."""
+    spec = get_spec(name)
+    pb = pxd.Problem.from_spec(spec)
+    st = geometry.build_structure(spec)
+    freqs, below = near_series_switch_freqs(st)
+    assert below[0] == 1.0 and 0.3 < below[1] < 0.7, below
     Z = pb.fill(freqs, n_threads=4)
     Zo = np.stack([efie.fill(st, f) for f in freqs])
     assert np.array_equal(Z, np.transpose(Z, (0, 2, 1)))

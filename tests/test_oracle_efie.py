@@ -192,3 +192,70 @@ def test_lossy_medium_dissipates():
     # adding loss raises the dissipated power for a uniform current pattern
     x = np.ones(st.M)
     assert np.real(x @ Z @ x) > np.real(x @ lossless @ x)
+
+
+def test_near_pair_remainder_in_both_branches():
+    """On near pairs the source integral takes the smooth remainder
+    (exp(-jkR) - 1)/(4 pi R) from a short series where |kR| < 1e-3 and from
+    the exponential above.  Both branches are pinned to the remainder's
+    low-frequency expansion (-jk - k^2 R/2 + j k^3 R^2/6 - ...)/(4 pi),
+    integrated over the source triangle (area A, centroid c):
+
+    * first order: -jk A / (4 pi) (the weights sum to one), and nothing for
+      the first moment (the points' weighted mean is the centroid);
+    * second order: -k^2 A sum_j w_j R_j / (8 pi), and the same with
+      (r_j - c) for the first moment;
+    * third order: j k^3 A mean(R^2) / (24 pi), where the degree-3 rule
+      integrates R^2 exactly: mean(R^2) = |r - c|^2 + (a^2 + b^2 + c^2) / 36
+      (the polar moment of a triangle about its centroid).
+
+    A dropped term, a wrong sign or a wrong coefficient up to the third order
+    in either branch fails one of these."""
+    spec = get_spec("plain8")
+    st = geometry.build_structure(spec)
+    T = st.tri_xyz()
+    td = efie.TriangleData(T)
+    tp = np.arange(0, len(T), 7)[:12]
+    tq = np.arange(len(T))
+    ip, iq = np.nonzero(efie.near_pairs(td, tp, tq))
+    ri = td.qp[tp][ip]                                   # (K, 4, 3) test points
+    rj = td.qp[tq][iq]                                   # (K, 4, 3) source points
+    cq = td.centroid[tq][iq]                             # (K, 3)
+    A = td.area[tq][iq][:, None]                         # (K, 1)
+    R = np.linalg.norm(ri[:, :, None] - rj[:, None], axis=-1)  # (K, 4, 4)
+    rel = rj - cq[:, None]
+    v = T[tq][iq]
+    e2 = sum(np.sum((v[:, (i + 1) % 3] - v[:, i]) ** 2, axis=-1) for i in range(3))
+    mean_r2 = np.sum((ri - cq[:, None]) ** 2, axis=-1) + e2[:, None] / 36.0
+    assert np.allclose(R ** 2 @ QUAD_W, mean_r2, rtol=1e-12)  # exactness of the rule on R^2
+
+    o1 = -A / (4 * np.pi)
+    o2 = -A * (R @ QUAD_W) / (8 * np.pi)
+    o2v = -A[..., None] * np.einsum("kij,j,kjd->kid", R, QUAD_W, rel) / (8 * np.pi)
+    o3 = A * mean_r2 / (24 * np.pi)
+    o3v = A[..., None] * np.einsum("kij,j,kjd->kid", R ** 2, QUAD_W, rel) / (24 * np.pi)
+
+    r_min, r_max = R[R > 0].min(), R.max()
+    SS0, SV0 = efie.source_integrals(td, tp, tq, 0j)
+    for k, branch in ((5e-4 / r_max, "series"), (1.5e-3 / r_min, "exponential")):
+        kr = k * r_max
+        nz = R > 0
+        # every nonzero distance falls on the branch named
+        assert (np.all(k * R[nz] < 1e-3) if branch == "series" else np.all(k * R[nz] > 1e-3)), branch
+        assert kr < 0.1
+        SS, SV = efie.source_integrals(td, tp, tq, k + 0j)
+        D = (SS - SS0)[ip, iq]                           # (K, 4)
+        DV = (SV - SV0)[ip, iq]                          # (K, 4, 3)
+        # relative size of the first neglected order at this k
+        tol = max(kr * kr, 1e-6)
+        c1 = D.imag / k
+        assert np.abs(c1 - o1).max() <= tol * np.abs(o1).max(), branch
+        c3 = (D.imag / k - o1) / k ** 2
+        assert np.abs(c3 - o3).max() <= 1e-2 * np.abs(o3).max(), branch
+        c2 = D.real / k ** 2
+        assert np.abs(c2 - o2).max() <= tol * np.abs(o2).max(), branch
+        assert np.abs(DV.imag / k).max() <= tol * np.abs(o1).max() * r_max, branch
+        c2v = DV.real / k ** 2
+        assert np.abs(c2v - o2v).max() <= tol * np.abs(o2v).max(), branch
+        c3v = DV.imag / k ** 3
+        assert np.abs(c3v - o3v).max() <= 1e-2 * np.abs(o3v).max(), branch
