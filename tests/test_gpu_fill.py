@@ -16,6 +16,7 @@ from oracle import efie, geometry, search
 from paper_2412_17617_amd import pxd
 from synth import get_spec
 
+from fill_common import near_series_switch_freqs
 from gpu_common import make_evaluator, oracle_parent
 
 pytestmark = pytest.mark.gpu
@@ -41,6 +42,29 @@ def test_device_fill_matches_oracle(name):
     print(f"{name}: M {pb.M}, max |dZ| / max |Z| = {err:.2e}")
     assert np.array_equal(Z, np.transpose(Z, (0, 2, 1)))
     assert err <= Z_RTOL
+
+
+@pytest.mark.parametrize("name", ["plain8", "tiny4x2"])
+def test_device_fill_across_the_near_series_switch(name):
+    """Near pairs evaluate the smooth remainder (exp(-jkR) - 1)/(4 pi R) by a
+    short series where |kR| < 1e-3 and by the exponential above; the band-edge
+    cases use the exponential only.  Here half of the near pairs' point
+    distances fall below the switch (f_mid), then all of them (f_mid / 3).
+    At f_mid a wrong second- or third-order coefficient of the series moves
+    the oracle's Z by 3e-8 or 6e-12 of max |Z| (tiny4x2; plain8 4e-8 and
+    1e-11), past the bar; the fourth order stays at rounding level."""
+    spec = get_spec(name)
+    pb = pxd.Problem.from_spec(spec)
+    st = geometry.build_structure(spec)
+    freqs, below = near_series_switch_freqs(st)
+    assert below[0] == 1.0 and 0.3 < below[1] < 0.7, below
+    Z = device_fill(pb, freqs)
+    Zo = np.stack([efie.fill(st, f) for f in freqs])
+    err = np.abs(Z - Zo).max(axis=(1, 2)) / np.abs(Zo).max(axis=(1, 2))
+    print(f"{name}: f {freqs[0]:.3e} {freqs[1]:.3e} Hz, near distances below the switch {below}, "
+          f"max |dZ| / max |Z| = {err[0]:.2e} {err[1]:.2e}")
+    assert np.array_equal(Z, np.transpose(Z, (0, 2, 1)))
+    assert err.max() <= Z_RTOL
 
 
 def test_device_fill_full_size():
