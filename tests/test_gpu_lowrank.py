@@ -131,6 +131,43 @@ def test_base_inverse_cache():
     ev.close()
 
 
+def test_base_map_churn():
+    """One context through a sequence of base maps of different active sizes
+    (N_B = 45, 29, 24, 33, 42 on the 4x4x2 stack), then back to the first
+    one twice, with a dense evaluation after every low-rank call: a new base
+    map always recomputes the inverse and the positions, nothing of the
+    previous map leaks into the next, the dense path leaves the cache alone
+    (the repeated map reuses it), and every call matches the dense path and
+    the oracle.  No candidate is beyond the low-rank limits, so no call takes
+    the dense fallback."""
+    spec = get_spec("tiny4x2")
+    st, Z, freqs = oracle_parent(spec)
+    off, cells = spec.flips()
+    seeds = (21, 22, 23, 24, 25, 21, 21)
+    ref = {}
+    for sd in sorted(set(seeds)):
+        base = bernoulli_map(spec.n_cells, 0.5, sd)
+        assert not over_limit(st, base, off, cells).any(), sd
+        ref[sd] = (base, *search.sweep(st, Z, base, off, cells, freqs))
+    ev, _ = make_evaluator(spec, Z, freqs)
+    prev = None
+    for k, sd in enumerate(seeds):
+        base, S_o, F_o = ref[sd]
+        print(f"churn step {k}: base map seed {sd}", flush=True)
+        S, F, status, am = ev.evaluate_flips_lowrank(base, off, cells)
+        stats = ev.stats()
+        S_d, F_d, _, am_d = ev.evaluate_flips(base, off, cells)
+        assert stats["base_reused"] == (1 if sd == prev else 0), (k, sd, stats)
+        assert stats["fallbacks"] == 0, (k, sd, stats)
+        assert np.all(status == 0)
+        assert np.abs(S - S_d).max() <= S_TOL, (k, sd)
+        assert np.abs(S - S_o).max() <= S_TOL, (k, sd)
+        assert np.all(np.abs(F - F_o) <= FOM_RTOL * np.abs(F_o)), (k, sd)
+        assert am == am_d or abs(F[am] - F[am_d]) <= FOM_RTOL * abs(F[am_d]), (k, sd)
+        prev = sd
+    ev.close()
+
+
 def test_full_batch_sampled():
     """20 x 20 x 2 batch (every single flip of the base map) at one frequency
     in the first passband: all candidates on the GPU, a seeded sample by the
